@@ -1,0 +1,397 @@
+"""Pins of the CPU oracle against facts fixed by geometry, not by the oracle itself.
+
+Each ``pin_*`` takes an oracle library handle so the same checks can be run against
+deliberately broken copies of the oracle (see test_oracle_mutants.py).  A pin raises
+AssertionError when the oracle disagrees with the closed form / invariant it checks.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction as Fr
+
+import numpy as np
+
+import oracle
+from oracle import exact
+from paper_1403_0802_amd.synth import Geometry, GridParams, star_ring
+
+
+def polygons(rings_per_feature):
+    """Geometry from a list of features, each a list of rings [(x, y), ...]."""
+    xs, ys, roff, froff = [], [], [0], [0]
+    for rings in rings_per_feature:
+        for r in rings:
+            a = np.asarray(r, dtype=np.float64)
+            xs.append(a[:, 0])
+            ys.append(a[:, 1])
+            roff.append(roff[-1] + len(a))
+        froff.append(froff[-1] + len(rings))
+    return Geometry("pip", np.asarray(roff, np.int64), np.concatenate(xs), np.concatenate(ys),
+                    np.asarray(froff, np.int64))
+
+
+def polylines(lines):
+    xs, ys, off = [], [], [0]
+    for ln in lines:
+        a = np.asarray(ln, dtype=np.float64)
+        xs.append(a[:, 0])
+        ys.append(a[:, 1])
+        off.append(off[-1] + len(a))
+    return Geometry("p2p", np.asarray(off, np.int64), np.concatenate(xs), np.concatenate(ys), None)
+
+
+def box(x0, y0, x1, y1, ccw=True, start=0):
+    r = [(x0, y0), (x1, y0), (x1, y1), (x0, y1)]
+    if not ccw:
+        r = r[::-1]
+    return r[start:] + r[:start]
+
+
+# ------------------------------------------------------------------------- PIP pins
+
+
+def pin_pip_boxes(lib, seed=1):
+    """Axis-aligned box [x0,x1) x [y0,y1): inside iff x0 <= px < x1 and y0 <= py < y1.
+    Every operation is sign-exact on these dyadic inputs, so the FP64 oracle must match
+    exactly, including points on edges and corners."""
+    rng = np.random.default_rng(seed)
+    for trial in range(40):
+        x0, x1 = sorted(rng.choice(np.arange(-16, 17), 2, replace=False) / 8.0)
+        y0, y1 = sorted(rng.choice(np.arange(-16, 17), 2, replace=False) / 8.0)
+        g = polygons([[box(x0, y0, x1, y1, ccw=bool(trial % 2), start=trial % 4)]])
+        grid = np.arange(-20, 21) / 8.0
+        px, py = np.meshgrid(grid, grid)
+        px, py = px.ravel(), py.ravel()
+        got = oracle.pip(g, px, py, lib=lib)
+        want = np.where((x0 <= px) & (px < x1) & (y0 <= py) & (py < y1), 0, -1)
+        assert np.array_equal(got, want), f"box trial {trial}"
+
+
+def pin_pip_hole(lib):
+    """Outer square with a square hole: inside iff in(outer) and not in(inner); a second,
+    overlapping polygon with a larger id never wins where the first one holds."""
+    outer = box(0.0, 0.0, 4.0, 4.0)
+    inner = box(1.0, 1.0, 3.0, 2.0, ccw=False)
+    g = polygons([[outer, inner], [box(2.0, 0.0, 6.0, 4.0)]])
+    grid = np.arange(-4, 53) / 8.0
+    px, py = np.meshgrid(grid, grid)
+    px, py = px.ravel(), py.ravel()
+    got = oracle.pip(g, px, py, lib=lib)
+    in0 = (0 <= px) & (px < 4) & (0 <= py) & (py < 4)
+    hole = (1 <= px) & (px < 3) & (1 <= py) & (py < 2)
+    in1 = (2 <= px) & (px < 6) & (0 <= py) & (py < 4)
+    want = np.where(in0 & ~hole, 0, np.where(in1, 1, -1))
+    assert np.array_equal(got, want)
+
+
+def pin_pip_convex(lib, seed=2):
+    """Convex polygons: inside iff the point is strictly left of every CCW edge (checked
+    only for points whose orientation against every edge is clear of zero)."""
+    rng = np.random.default_rng(seed)
+    for trial in range(20):
+        n = int(rng.integers(3, 40))
+        th = np.sort(rng.uniform(0, 2 * math.pi, n))
+        if trial % 2:
+            th = np.linspace(0, 2 * math.pi, n, endpoint=False) + rng.uniform()
+        cx, cy, r = rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(0.2, 2.0)
+        ring = list(zip(cx + r * np.cos(th), cy + r * np.sin(th)))
+        g = polygons([[ring]])
+        px = rng.uniform(cx - 1.2 * r, cx + 1.2 * r, 4000)
+        py = rng.uniform(cy - 1.2 * r, cy + 1.2 * r, 4000)
+        a = np.asarray(ring)
+        b = np.roll(a, -1, axis=0)
+        orient = ((b[:, 0] - a[:, 0])[None, :] * (py[:, None] - a[:, 1][None, :])
+                  - (b[:, 1] - a[:, 1])[None, :] * (px[:, None] - a[:, 0][None, :]))
+        clear = np.all(np.abs(orient) > 1e-9, axis=1)
+        want = np.where(np.all(orient > 0, axis=1), 0, -1)
+        got = oracle.pip(g, px, py, lib=lib)
+        assert np.array_equal(got[clear], want[clear]), f"convex trial {trial}"
+
+
+def pin_pip_star_sectors(lib, seed=3):
+    """Star polygons (the configuration-1 shape): find the angular sector [t_k, t_k+1] of
+    the point about the centre and test it against chord k only."""
+    rng = np.random.default_rng(seed)
+    for trial in range(10):
+        m = int(rng.integers(16, 257))
+        x, y, th, r = star_ring(rng, 0.5, 0.5, m, 0.3, 0.5)
+        g = polygons([[list(zip(x, y))]])
+        px = rng.uniform(0, 1, 5000)
+        py = rng.uniform(0, 1, 5000)
+        phi = np.mod(np.arctan2(py - 0.5, px - 0.5), 2 * math.pi)
+        k = np.searchsorted(th, phi, side="right") - 1  # -1: wraps to the last chord
+        k = np.where(k < 0, m - 1, k)
+        k2 = (k + 1) % m
+        ax, ay, bx, by = x[k], y[k], x[k2], y[k2]
+        side = (bx - ax) * (py - ay) - (by - ay) * (px - ax)  # > 0: centre side (CCW)
+        clear = np.abs(side) > 1e-9
+        want = np.where(side > 0, 0, -1)
+        got = oracle.pip(g, px, py, lib=lib)
+        assert np.array_equal(got[clear], want[clear]), f"star trial {trial}"
+
+
+def pin_pip_winding_and_exact(lib, seed=4):
+    """On simple rings, odd crossing parity <=> nonzero winding number (exact), and the
+    FP64 oracle equals the exact even-odd predicate except within 1e-12 of an edge."""
+    rng = np.random.default_rng(seed)
+    for trial in range(6):
+        m = int(rng.integers(5, 24))
+        x, y, _, _ = star_ring(rng, 0.0, 0.0, m, 0.2, 1.0)
+        ring = list(zip(x.tolist(), y.tolist()))
+        hole_x, hole_y, _, _ = star_ring(rng, 0.05, -0.03, 7, 0.05, 0.12)
+        hole = list(zip(hole_x.tolist(), hole_y.tolist()))
+        g = polygons([[ring, hole]])
+        pts = [(float(a), float(b)) for a, b in rng.uniform(-1.1, 1.1, (300, 2))]
+        # points exactly at vertex heights and exactly on vertices
+        pts += [(float(rng.uniform(-1, 1)), vy) for vy in y[:5].tolist()]
+        pts += [(vx, vy) for vx, vy in ring[:3]]
+        px = np.array([p[0] for p in pts])
+        py = np.array([p[1] for p in pts])
+        got = oracle.pip(g, px, py, lib=lib)
+        for (qx, qy), gid in zip(pts, got):
+            w_outer = exact.winding_number(qx, qy, ring)
+            w_hole = exact.winding_number(qx, qy, hole)
+            ex = exact.inside_exact(qx, qy, [ring, hole])
+            near = min(exact.distance_to_ring_boundary_lb(qx, qy, ring),
+                       exact.distance_to_ring_boundary_lb(qx, qy, hole)) <= Fr(1, 10 ** 24)
+            if not near:
+                assert ex == ((w_outer != 0) != (w_hole != 0)), (qx, qy)
+                assert (gid == 0) == ex, (qx, qy)
+            elif (qx, qy) in ring:
+                # a vertex: the half-open rule is decided exactly even in FP64 because
+                # every product involves an exact zero
+                assert (gid == 0) == ex, (qx, qy)
+
+
+def pin_pip_grid_equals_brute(lib, seed=5):
+    """Filter soundness: the grid-filtered result equals brute force over all polygons."""
+    from paper_1403_0802_amd import synth
+    w = synth.config1(n_points=20_000, grid_n=6, seed_salt=seed)
+    b = oracle.pip(w.geom, w.px, w.py, None, lib=lib)
+    assert (b >= 0).mean() > 0.2
+    # the configured extent, and an extent derived from the MBBs (nx = ny = 0)
+    for params in (w.params, GridParams(cell_size=w.params.cell_size)):
+        g = oracle.build_grid(w.geom, params, lib)
+        a = oracle.pip(w.geom, w.px, w.py, g, lib=lib)
+        assert np.array_equal(a, b)
+    # polygon vertices themselves lie on the MBB boundary: the filter must keep them
+    g = oracle.build_grid(w.geom, GridParams(cell_size=w.params.cell_size), lib)
+    a = oracle.pip(w.geom, w.geom.x, w.geom.y, g, lib=lib)
+    assert np.array_equal(a, oracle.pip(w.geom, w.geom.x, w.geom.y, None, lib=lib))
+
+
+# ------------------------------------------------------------------------- P2P pins
+
+
+def pin_p2p_single_segment(lib):
+    """Segment (0,0)-(L,0): d = |y| over the segment, else the nearer endpoint; exact on
+    dyadic inputs, and Pythagorean triples give exact distances in every case."""
+    L = 6.0
+    for qx in np.arange(-8, 57) / 4.0:
+        for qy in (-3.0, -0.5, 0.0, 0.25, 2.0):
+            d2 = oracle.segment_d2(qx, qy, 0.0, 0.0, L, 0.0, lib)
+            ex = 0.0 if 0 <= qx <= L else min(qx * qx, (qx - L) ** 2)
+            assert d2 == ex + qy * qy, (qx, qy, d2)
+    # segment (0,0)-(4,3), |ab| = 5; points at distance exactly 5 in each of the 3 cases
+    cases = [(-3.0, 4.0), (1.0, 7.0), (-1.0, 5.5), (4.0 + 3.0, 3.0 - 4.0), (-4.0, -3.0)]
+    for qx, qy in cases:
+        d2 = oracle.segment_d2(qx, qy, 0.0, 0.0, 4.0, 3.0, lib)
+        assert d2 == 25.0, (qx, qy, d2)
+    # degenerate segment: distance to the single point
+    assert oracle.segment_d2(3.0, 4.0, 0.0, 0.0, 0.0, 0.0, lib) == 25.0
+    # a point on the segment is at distance 0
+    assert oracle.segment_d2(2.0, 1.5, 0.0, 0.0, 4.0, 3.0, lib) == 0.0
+
+
+def pin_p2p_symmetries(lib, seed=6):
+    """Swapping x and y, 90-degree rotations and reflections leave d^2 bitwise
+    unchanged; so does an exact translation of integer inputs."""
+    rng = np.random.default_rng(seed)
+    for _ in range(2000):
+        p, a, b = rng.uniform(-100, 100, (3, 2))
+        d = oracle.segment_d2(p[0], p[1], a[0], a[1], b[0], b[1], lib)
+        assert oracle.segment_d2(p[1], p[0], a[1], a[0], b[1], b[0], lib) == d
+        assert oracle.segment_d2(-p[1], p[0], -a[1], a[0], -b[1], b[0], lib) == d
+        assert oracle.segment_d2(-p[0], p[1], -a[0], a[1], -b[0], b[1], lib) == d
+        assert oracle.segment_d2(p[0], -p[1], a[0], -a[1], b[0], -b[1], lib) == d
+        pi, ai, bi = np.rint(rng.uniform(-1000, 1000, (3, 2)))
+        t = np.rint(rng.uniform(-1e6, 1e6, 2))
+        d0 = oracle.segment_d2(pi[0], pi[1], ai[0], ai[1], bi[0], bi[1], lib)
+        d1 = oracle.segment_d2(pi[0] + t[0], pi[1] + t[1], ai[0] + t[0], ai[1] + t[1],
+                               bi[0] + t[0], bi[1] + t[1], lib)
+        assert d0 == d1
+
+
+def pin_p2p_lipschitz_and_exact(lib, seed=7):
+    """Distance is 1-Lipschitz in p, and the FP64 d^2 is within a few ulps of the exact
+    clamped-projection value (a different formulation)."""
+    rng = np.random.default_rng(seed)
+    for _ in range(400):
+        a, b = rng.uniform(-50, 50, (2, 2))
+        p = rng.uniform(-80, 80, 2)
+        q = p + rng.normal(0, 3, 2)
+        dp = math.sqrt(oracle.segment_d2(*p, *a, *b, lib))
+        dq = math.sqrt(oracle.segment_d2(*q, *a, *b, lib))
+        assert abs(dp - dq) <= float(np.hypot(*(p - q))) * (1 + 1e-12) + 1e-12
+        ex = exact.segment_d2_exact(*p, *a, *b)
+        got = Fr(oracle.segment_d2(*p, *a, *b, lib))
+        scale = Fr(float(np.sum((p - a) ** 2) + np.sum((b - a) ** 2)))
+        assert abs(got - ex) <= scale * Fr(1, 2 ** 48), (p, a, b)
+
+
+def pin_p2p_brute_exact(lib, seed=8):
+    """Tiny inputs: the oracle's nearest polyline equals the exact one (when the exact
+    top two are not within 1e-9 relative), with ties and range both inclusive."""
+    rng = np.random.default_rng(seed)
+    lines = []
+    for _ in range(12):
+        m = int(rng.integers(2, 7))
+        st = rng.uniform(0, 100, 2)
+        lines.append(np.cumsum(np.vstack([st, rng.uniform(-20, 20, (m - 1, 2))]), axis=0))
+    g = polylines(lines)
+    px, py = rng.uniform(-10, 110, (2, 300))
+    D = 15.0
+    ids, dist = oracle.p2p(g, px, py, D, None, lib=lib)
+    for i in range(len(px)):
+        ds = [exact.polyline_d2_exact(px[i], py[i], ln[:, 0], ln[:, 1]) for ln in lines]
+        order = sorted(range(len(ds)), key=lambda k: (ds[k], k))
+        best = order[0]
+        if ds[best] > Fr(D) * Fr(D):
+            if ds[best] > Fr(D) * Fr(D) * (1 + Fr(1, 10 ** 9)):
+                assert ids[i] == -1 and math.isinf(dist[i])
+            continue
+        if abs(ds[order[1]] - ds[best]) <= ds[best] * Fr(1, 10 ** 9):
+            continue
+        if ds[best] >= Fr(D) * Fr(D) * (1 - Fr(1, 10 ** 9)):
+            continue
+        assert ids[i] == best, i
+        # the cross product cancels near the line, so the error is absolute, scaled by
+        # the squared coordinate magnitude (here <= 300^2)
+        assert abs(Fr(dist[i]) ** 2 - ds[best]) <= Fr(300 ** 2, 2 ** 48)
+
+
+def pin_p2p_ties_and_range(lib):
+    """Two polylines at exactly equal distance: the smaller id wins; distance exactly D
+    is inside the range (inclusive), a hair beyond it is not."""
+    g = polylines([[(0.0, 2.0), (10.0, 2.0)], [(0.0, -2.0), (10.0, -2.0)],
+                   [(0.0, 5.0), (10.0, 5.0)]])
+    ids, dist = oracle.p2p(g, np.array([5.0, 5.0, 5.0]), np.array([0.0, 3.0, 7.0]), 2.0, None,
+                           lib=lib)
+    assert ids.tolist() == [0, 0, 2] and dist.tolist() == [2.0, 1.0, 2.0]
+    ids, dist = oracle.p2p(g, np.array([5.0]), np.array([np.nextafter(-4.0, -5.0)]), 2.0, None,
+                           lib=lib)
+    assert ids.tolist() == [-1] and math.isinf(dist[0])
+    # the same winner with ids reversed in order: id 0 still wins a tie
+    g2 = polylines([[(0.0, -2.0), (10.0, -2.0)], [(0.0, 2.0), (10.0, 2.0)]])
+    ids, _ = oracle.p2p(g2, np.array([5.0]), np.array([0.0]), 3.0, None, lib=lib)
+    assert ids.tolist() == [0]
+
+
+def pin_p2p_grid_equals_brute(lib, seed=9):
+    from paper_1403_0802_amd import synth
+    w = synth.config2(n_points=20_000, n_lines=600, seed_salt=seed)
+    # a denser subset of polylines keeps the brute force small
+    g = oracle.build_grid(w.geom, w.params, lib)
+    a_id, a_d = oracle.p2p(w.geom, w.px, w.py, w.params.radius_D, g, lib=lib)
+    b_id, b_d = oracle.p2p(w.geom, w.px, w.py, w.params.radius_D, None, lib=lib)
+    assert np.array_equal(a_id, b_id)
+    assert np.array_equal(a_d, b_d)
+    assert (a_id >= 0).sum() > 50
+
+
+# ------------------------------------------------------------------------- grid pins
+
+
+def pin_grid_definition(lib, seed=10):
+    """Cells, candidate lists, stable point order and test counts equal their plain
+    definitions computed with numpy (floor of the offset over the cell size; every cell
+    an MBB touches; numpy's stable argsort)."""
+    from paper_1403_0802_amd import synth
+    rng = np.random.default_rng(seed)
+    # MBB sides exactly on cell lines: the pad decides whether the cell below is paired
+    on_lines = synth.Workload(
+        "on_lines", "pip",
+        polygons([[box(0.25, 0.5, 0.75, 0.625)], [box(0.125, 0.0, 0.5, 0.25, start=2)]]),
+        rng.uniform(0, 1, 2000), rng.uniform(0, 1, 2000),
+        GridParams(cell_size=1.0 / 64, nx=64, ny=64), {})
+    on_lines_p2p = synth.Workload(
+        "on_lines_p2p", "p2p", polylines([[(2.0, 3.0), (4.5, 3.0)], [(1.0, 1.0), (1.0, 6.0)]]),
+        rng.uniform(0, 8, 2000), rng.uniform(0, 8, 2000),
+        GridParams(cell_size=0.5, radius_D=0.5, nx=16, ny=16), {})
+    for w in (on_lines, on_lines_p2p,
+              synth.config1(n_points=30_000, grid_n=5, seed_salt=seed),
+              synth.config2(n_points=30_000, n_lines=800, seed_salt=seed)):
+        params = w.params
+        g = oracle.build_grid(w.geom, params, lib)
+        # points outside the extent (just past each side, far away, non-finite) too
+        span = g.cs * g.nx
+        ex = np.array([g.x0 - 1e-9 * span, g.x0 + span, g.x0 + 2 * span, np.nan, np.inf,
+                       g.x0, g.x0 + np.nextafter(span, 0)])
+        w.px = np.concatenate([w.px, ex, np.full(len(ex), g.x0 + 0.5 * span)])
+        w.py = np.concatenate([w.py, np.full(len(ex), g.y0 + 0.5 * span), ex])
+        cells = oracle.point_cells(g, w.px, w.py, lib)
+        fx = np.floor((w.px - g.x0) / g.cs)
+        fy = np.floor((w.py - g.y0) / g.cs)
+        ok = (fx >= 0) & (fx < g.nx) & (fy >= 0) & (fy < g.ny)
+        want = np.where(ok, fy * g.nx + fx, -1).astype(np.int64)
+        assert np.array_equal(cells, want)
+        pt_off, perm = oracle.sort_points(g, cells, lib)
+        key = np.where(cells < 0, g.ncells, cells)
+        assert np.array_equal(perm, np.argsort(key, kind="stable"))
+        assert np.array_equal(pt_off, np.searchsorted(np.sort(key), np.arange(g.ncells + 1)))
+        # MBBs and rasterisation, written out from the definition
+        pad = g.cs * 2.0 ** -20
+        D = params.radius_D if w.kind == "p2p" else 0.0
+        rvo = w.geom.ring_vert_off
+        fro = w.geom.feature_ring_off if w.kind == "pip" else np.arange(w.geom.n_features + 1)
+        lists = [[] for _ in range(g.ncells)]
+        for f in range(w.geom.n_features):
+            v0, v1 = rvo[fro[f]], rvo[fro[f + 1]]
+            xs, ys = w.geom.x[v0:v1], w.geom.y[v0:v1]
+            lo_x, hi_x = (xs.min() - D) - pad, (xs.max() + D) + pad
+            lo_y, hi_y = (ys.min() - D) - pad, (ys.max() + D) + pad
+            if w.kind == "pip":
+                lo_x, hi_x, lo_y, hi_y = xs.min() - pad, xs.max() + pad, ys.min() - pad, ys.max() + pad
+            ax = int(max(0, math.floor((lo_x - g.x0) / g.cs)))
+            bx = int(min(g.nx - 1, math.floor((hi_x - g.x0) / g.cs)))
+            ay = int(max(0, math.floor((lo_y - g.y0) / g.cs)))
+            by = int(min(g.ny - 1, math.floor((hi_y - g.y0) / g.cs)))
+            for iy in range(ay, by + 1):
+                for ix in range(ax, bx + 1):
+                    lists[iy * g.nx + ix].append(f)
+        off = np.concatenate([[0], np.cumsum([len(l) for l in lists])])
+        assert np.array_equal(g.cand_off, off)
+        assert np.array_equal(g.cand_id, np.asarray([f for l in lists for f in l], np.int32))
+        npts = np.diff(pt_off)[: g.ncells]
+        ne = oracle.nedges_of(w.geom)
+        tests = sum(int(npts[c]) * int(sum(ne[f] for f in lists[c])) for c in range(g.ncells))
+        assert oracle.test_count(g, w.px, w.py, lib) == tests
+
+
+def pin_tessellation(lib, seed=11):
+    """A watertight tessellation of the unit square: every point is claimed by exactly
+    one polygon, unless it lies in a hole (checked with the exact predicate)."""
+    from paper_1403_0802_amd import synth
+    geom, _ = synth.config3_geometry(n_polygons=60, median_v=40, max_v=400, hole_frac=0.3,
+                                     seed_salt=seed)
+    rng = np.random.default_rng(seed)
+    px, py = rng.uniform(0, 1, (2, 20_000))
+    cnt = oracle.pip_count(geom, px, py, lib=lib)
+    assert cnt.max() <= 1
+    zero = np.nonzero(cnt == 0)[0]
+    assert len(zero) < 0.2 * len(px)
+    fro, rvo = geom.feature_ring_off, geom.ring_vert_off
+    holes = []
+    for f in range(geom.n_features):
+        for r in range(fro[f] + 1, fro[f + 1]):
+            holes.append(list(zip(geom.x[rvo[r]:rvo[r + 1]].tolist(),
+                                  geom.y[rvo[r]:rvo[r + 1]].tolist())))
+    for i in zero[:200]:
+        assert any(exact.inside_exact(px[i], py[i], [h]) for h in holes), (px[i], py[i])
+
+
+ALL_PINS = [pin_pip_boxes, pin_pip_hole, pin_pip_convex, pin_pip_star_sectors,
+            pin_pip_winding_and_exact, pin_pip_grid_equals_brute, pin_p2p_single_segment,
+            pin_p2p_symmetries, pin_p2p_lipschitz_and_exact, pin_p2p_brute_exact,
+            pin_p2p_ties_and_range, pin_p2p_grid_equals_brute, pin_grid_definition,
+            pin_tessellation]
