@@ -1,0 +1,232 @@
+/*
+ * gp.h -- C ABI of the MI355X refinement library for grid-filtered spatial joins.
+ *
+ * The library computes the two refinement operations of Zhang & You, "Large-Scale
+ * Geospatial Processing on Multi-Core and Many-Core Processors" (arXiv 1403.0802):
+ *
+ *   PIP  (Sec. III.C, Fig. 3): for each point, the polygon it falls within, by the
+ *        even-odd ray-crossing rule over every ring (outer ring and holes).
+ *   P2P  (Sec. III.B, Fig. 2): for each point, the nearest polyline within range D,
+ *        where a polyline's distance is the minimum point-segment distance over its
+ *        segments (perpendicular distance when the projection falls on the segment,
+ *        else the nearer endpoint).
+ *
+ * Both sit behind the paper's filter (Sec. III.A): a uniform grid pairs each point
+ * cell with the features whose MBB (expanded by D for P2P) touches that cell, and
+ * only those (cell, {feature}) pairs are refined.
+ *
+ * Exact definitions used by the library (the paper leaves these open):
+ *   - Grid: cell = (floor((x-x0)/cs), floor((y-y0)/cs)), row-major id cy*nx+cx; a
+ *     point outside [0,nx)x[0,ny) or with a non-finite coordinate is unpaired.
+ *     Each MBB is padded by cs*2^-20 on every side (after the +-D expansion for
+ *     P2P) before it is rasterised; cells are clamped to the grid.
+ *   - PIP crossing of edge (a,b): none if a.y == b.y; else with lo/hi the lower and
+ *     upper endpoint, lo.y <= p.y < hi.y and
+ *     (p.x-lo.x)*(hi.y-lo.y) < (hi.x-lo.x)*(p.y-lo.y), each product rounded once.
+ *     A point takes the SMALLEST polygon id with odd crossing parity, else -1.
+ *   - P2P segment distance: dx=b.x-a.x, dy=b.y-a.y, wx=p.x-a.x, wy=p.y-a.y,
+ *     L2=dx*dx+dy*dy, t=wx*dx+wy*dy; t<=0: wx*wx+wy*wy; t>=L2: |p-b|^2;
+ *     else (wx*dy-wy*dx)^2/L2.  A point takes the polyline with the smallest d^2
+ *     among those with d^2 <= D*D (ties: smallest id) and distance sqrt(d^2); with
+ *     no such polyline, id -1 and distance +inf.
+ *
+ * Precision forms:
+ *   GP_FP64  every test in FP64 with exactly the operation order above (results are
+ *            bitwise reproducible against a scalar FP64 implementation).
+ *   GP_MIXED tests in FP32 on coordinates rebased to each grid cell's centre, with a
+ *            per-edge guard band; any point whose FP32 decision could differ from the
+ *            FP64 one is recomputed in FP64 on the GPU.  PIP ids and P2P ids are
+ *            identical to GP_FP64; a P2P distance that is not recomputed carries an
+ *            absolute error of at most 16*2^-24*(|cell half-diagonal| + M), M the
+ *            largest rebased vertex magnitude among the segments near the cell.
+ *
+ * Conventions:
+ *   - All calls return a gp_status; 0 is success.  gp_last_error() returns a
+ *     thread-local message for the last failing call on the calling thread.
+ *   - Query calls are asynchronous on the caller's HIP stream (hipStream_t passed as
+ *     void*; NULL means the default stream).  Argument errors are reported
+ *     synchronously; device faults surface as GP_E_HIP on a later call.
+ *   - The library never allocates memory inside gp_pip / gp_p2p: the caller passes a
+ *     device workspace of at least gp_workspace_bytes() bytes.
+ *   - Ids are int32; sizes are int64 but every count must stay below 2^31.
+ */
+#ifndef GP_H
+#define GP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gp_status;
+#define GP_OK 0
+#define GP_E_INVALID_ARG (-1)  /* bad pointer, size, enum or option */
+#define GP_E_BAD_GEOMETRY (-2) /* malformed offsets, non-finite vertex, short polyline */
+#define GP_E_OOM (-3)          /* device or host allocation failed */
+#define GP_E_HIP (-4)          /* a HIP runtime call failed */
+#define GP_E_CAPACITY (-5)     /* a count exceeds what the library supports */
+#define GP_E_BUSY (-6)         /* server: no admission possible right now */
+#define GP_E_CLOSED (-7)       /* server: already shut down */
+#define GP_E_TIMEOUT (-8)      /* server: wait timed out */
+#define GP_E_NOT_FOUND (-9)    /* server: unknown ticket */
+
+typedef enum { GP_PIP = 1, GP_P2P = 2 } gp_kind;
+typedef enum { GP_FP64 = 0, GP_MIXED = 1 } gp_precision;
+
+/* Thread-local text of the last error on this thread (never NULL). */
+const char *gp_last_error(void);
+
+/* Features in SoA + CSR form (Sec. III.A-B: count vectors and prefix-sum offsets
+ * instead of objects).  Polygon f owns rings feature_ring_off[f]..[f+1]; ring r owns
+ * vertices ring_vert_off[r]..[r+1] of x/y.  Rings are implicitly closed; a repeated
+ * closing vertex is a harmless zero-length edge.  Polylines: feature_ring_off is NULL,
+ * feature f is the vertex chain of ring f, n_rings == n_features, and every polyline
+ * needs >= 2 vertices.  Offsets start at 0, never decrease, and end at the total. */
+typedef struct gp_geometry {
+    int64_t n_features;
+    const int64_t *feature_ring_off; /* [n_features+1], polygons only */
+    int64_t n_rings;
+    const int64_t *ring_vert_off;    /* [n_rings+1] */
+    int64_t n_vertices;
+    const double *x;                 /* [n_vertices] */
+    const double *y;                 /* [n_vertices] */
+    int32_t on_device;               /* 1: the five arrays are device pointers */
+} gp_geometry;
+
+/* Grid of cell size cell_size > 0.  nx == 0 or ny == 0 derives the extent from the
+ * (expanded, padded) MBBs: x0 = smallest MBB corner, nx = floor((max-x0)/cs)+1.
+ * radius_D >= 0 is the P2P range (ignored for PIP). */
+typedef struct gp_grid_params {
+    double cell_size;
+    double radius_D;
+    double x0, y0;
+    int64_t nx, ny;
+} gp_grid_params;
+
+typedef struct gp_grid gp_grid;
+
+/* Kernel configuration chosen by gp_autotune or set by hand (0 = library default). */
+typedef struct gp_tuning {
+    int32_t points_per_lane; /* 1, 2 or 4: a work item holds up to 64*ppl points */
+    int32_t edge_chunk;      /* edges staged in LDS per round: 64..512, multiple of 64 */
+    int32_t wg_per_cu;       /* persistent workgroups per compute unit: 1..32 */
+    int32_t persistent;      /* 1: persistent work queue; 0: one workgroup per item */
+} gp_tuning;
+
+/* Per-call counters.  Filling them synchronises the stream at the end of the call. */
+typedef struct gp_stats {
+    int64_t n_points;     /* points in the call */
+    int64_t n_paired;     /* points in a cell with >= 1 candidate */
+    int64_t n_items;      /* refinement work items (cell, point chunk) */
+    uint64_t tests;       /* point-edge tests: sum over cells npts * sum nedges(cands) */
+    int64_t n_rechecked;  /* GP_MIXED: points recomputed in FP64 */
+    float ms_pairing;     /* hash + sort + gather + item list */
+    float ms_refine;      /* refinement kernel */
+    float ms_recheck;     /* FP64 recheck kernel */
+    float ms_total;
+} gp_stats;
+
+/* Build the device-resident grid for a feature set (Sec. III.A filter):
+ * validates the geometry, copies it to the device, derives MBBs (expanded by D for
+ * P2P), rasterises them and sorts the (cell, feature) pairs into a cell -> candidate
+ * CSR whose lists are sorted by feature id.  Synchronous on hip_stream; the grid owns
+ * its device memory until gp_grid_free.  GP_E_BAD_GEOMETRY for malformed input,
+ * GP_E_CAPACITY when a count reaches 2^31 or the grid exceeds 2^28 cells. */
+gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom, const gp_grid_params *params,
+                        void *hip_stream, gp_grid **out);
+void gp_grid_free(gp_grid *grid);
+
+/* Grid description.  Any output pointer may be NULL. */
+typedef struct gp_grid_info {
+    int32_t kind;
+    double x0, y0, cell_size, radius_D;
+    int64_t nx, ny, n_features, n_edges, n_pairs;
+} gp_grid_info;
+gp_status gp_grid_get_info(const gp_grid *grid, gp_grid_info *info);
+
+/* Copy the candidate CSR to HOST buffers: cand_off[nx*ny+1], cand_id[n_pairs]. */
+gp_status gp_grid_candidates(const gp_grid *grid, int32_t *cand_off, int32_t *cand_id);
+
+/* Device workspace needed by gp_pip / gp_p2p / gp_pair_points for n points. */
+gp_status gp_workspace_bytes(const gp_grid *grid, int64_t n_points, gp_precision prec,
+                             size_t *bytes);
+
+/* Point pairing only (Sec. III.A): cell hash and stable counting sort.  Writes, to
+ * DEVICE buffers, perm[n] (sorted position -> original index; points of a cell in
+ * ascending original index, unpaired points last) and pt_off[nx*ny+1] (start of each
+ * cell in perm).  Asynchronous. */
+gp_status gp_pair_points(const gp_grid *grid, int64_t n, const double *px, const double *py,
+                         int32_t *perm, int32_t *pt_off, void *ws, size_t ws_bytes,
+                         void *hip_stream);
+
+/* PIP refinement for n points (device pointers px, py, out_id).  out_id[i] = smallest
+ * polygon id containing point i under the even-odd rule, or -1.  Asynchronous. */
+gp_status gp_pip(const gp_grid *grid, int64_t n, const double *px, const double *py,
+                 int32_t *out_id, gp_precision prec, void *ws, size_t ws_bytes,
+                 void *hip_stream, gp_stats *stats);
+
+/* P2P refinement for n points (device pointers).  out_id[i] = nearest polyline within
+ * D (ties: smallest id) or -1; out_dist[i] its distance or +inf.  Asynchronous. */
+gp_status gp_p2p(const gp_grid *grid, int64_t n, const double *px, const double *py,
+                 int32_t *out_id, double *out_dist, gp_precision prec, void *ws,
+                 size_t ws_bytes, void *hip_stream, gp_stats *stats);
+
+/* Kernel configuration of a grid for one precision form. */
+gp_status gp_set_tuning(gp_grid *grid, gp_precision prec, const gp_tuning *tuning);
+gp_status gp_get_tuning(const gp_grid *grid, gp_precision prec, gp_tuning *tuning);
+
+/* Autotuner: times every configuration of a built-in search space on the given
+ * (device) sample points, keeps the fastest, stores it in the grid and returns it.
+ * Results never depend on the configuration.  Synchronous. */
+gp_status gp_autotune(gp_grid *grid, gp_precision prec, int64_t n, const double *px,
+                      const double *py, void *ws, size_t ws_bytes, void *hip_stream,
+                      gp_tuning *best, float *best_ms);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A continuous-batching server over resident grids.  Requests are admitted while a
+ * slot and enough of the memory budget are free; each slot runs its requests on its
+ * own HIP stream, so work from different requests overlaps on the device.  Requests
+ * larger than a slot are processed in slot-sized chunks (points are independent). */
+typedef struct gp_serve_opts {
+    int32_t n_slots;          /* concurrent requests on the device, 1..16 */
+    int64_t slot_points;      /* points per slot chunk (capacity of one slot) */
+    int64_t mem_budget;       /* bytes of device memory the server may use */
+    int32_t precision;        /* gp_precision for every request */
+    int32_t inputs_on_device; /* 1: submit() pointers are device memory, else host */
+    int32_t use_graphs;       /* 1: replay captured hipGraphs per slot and size bucket */
+    int32_t max_queue;        /* pending requests beyond which submit returns BUSY */
+} gp_serve_opts;
+
+typedef struct gp_server gp_server;
+
+typedef struct gp_serve_stats {
+    int64_t completed, failed, pending, in_flight;
+    double p50_us, p99_us, mean_us, max_us; /* submit -> result visible */
+    double points_per_s, tests_per_s;       /* over the completed requests' busy span */
+    int64_t points, tests, graph_replays;
+} gp_serve_stats;
+
+/* pip_grid / p2p_grid may each be NULL (then that kind is rejected). */
+gp_status gp_serve_create(const gp_grid *pip_grid, const gp_grid *p2p_grid,
+                          const gp_serve_opts *opts, gp_server **out);
+/* Enqueue a request; returns immediately with a ticket.  out_id (and out_dist for P2P)
+ * are written before the ticket completes; they live where the inputs live. */
+gp_status gp_serve_submit(gp_server *srv, gp_kind kind, int64_t n, const double *px,
+                          const double *py, int32_t *out_id, double *out_dist,
+                          uint64_t *ticket);
+/* done = 1 once the ticket's results are visible (0 while pending). */
+gp_status gp_serve_poll(gp_server *srv, uint64_t ticket, int32_t *done);
+/* Block until the ticket completes or timeout_us passes (<0: forever). Returns the
+ * request's own status once complete; GP_E_TIMEOUT otherwise. */
+gp_status gp_serve_wait(gp_server *srv, uint64_t ticket, int64_t timeout_us);
+gp_status gp_serve_stats_get(gp_server *srv, gp_serve_stats *stats);
+/* Drain in-flight work, stop the server thread and free everything. */
+gp_status gp_serve_destroy(gp_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GP_H */

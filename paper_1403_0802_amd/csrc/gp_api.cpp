@@ -1,0 +1,621 @@
+// Host runtime behind include/gp.h: argument checks, the device-resident grid, the
+// workspace layout, launch sequencing of the query pipeline, and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "gp_internal.h"
+
+using namespace gp;
+
+struct gp_grid : public gp::Grid {};
+
+// ------------------------------------------------------------------------- errors
+
+static thread_local char g_err[512] = "no error";
+
+extern "C" const char *gp_last_error(void) { return g_err; }
+
+namespace gp {
+gp_status set_error(gp_status code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+}  // namespace gp
+
+#define GP_TRY_HIP(expr)                                                                  \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return set_error(GP_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+  } while (0)
+
+static const int64_t kMaxCount = 0x7fffffffLL;
+static const int64_t kMaxCells = (int64_t)1 << 28;
+
+// ------------------------------------------------------------------------- helpers
+
+static int bits_for(uint64_t v) {
+  int b = 0;
+  while (v) { ++b; v >>= 1; }
+  return b;
+}
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+namespace {
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 16); }
+  template <class T> T *as() const { return (T *)p; }
+};
+}  // namespace
+
+static gp_tuning default_tuning(gp_kind kind, gp_precision prec) {
+  gp_tuning t;
+  t.points_per_lane = (prec == GP_MIXED) ? 2 : 1;
+  t.edge_chunk = (kind == GP_PIP) ? 256 : 256;
+  t.wg_per_cu = 8;
+  t.persistent = 1;
+  return t;
+}
+
+static bool tuning_valid(const gp_tuning &t) {
+  return (t.points_per_lane == 1 || t.points_per_lane == 2 || t.points_per_lane == 4) &&
+         t.edge_chunk >= 64 && t.edge_chunk <= 512 && t.edge_chunk % 64 == 0 &&
+         t.wg_per_cu >= 1 && t.wg_per_cu <= 32 && (t.persistent == 0 || t.persistent == 1);
+}
+
+// ------------------------------------------------------------------------- geometry checks
+
+namespace {
+struct HostGeom {
+  std::vector<int64_t> fro, rvo;
+  std::vector<double> x, y;
+};
+}  // namespace
+
+template <class T>
+static hipError_t fetch(std::vector<T> &dst, const T *src, size_t n, bool on_device) {
+  dst.resize(n);
+  if (n == 0) return hipSuccess;
+  if (on_device) return hipMemcpy(dst.data(), src, n * sizeof(T), hipMemcpyDeviceToHost);
+  memcpy(dst.data(), src, n * sizeof(T));
+  return hipSuccess;
+}
+
+static gp_status check_offsets(const std::vector<int64_t> &off, int64_t end, const char *what) {
+  if (off.empty() || off[0] != 0)
+    return set_error(GP_E_BAD_GEOMETRY, "%s must start at 0", what);
+  for (size_t i = 1; i < off.size(); ++i)
+    if (off[i] < off[i - 1])
+      return set_error(GP_E_BAD_GEOMETRY, "%s decreases at %zu", what, i);
+  if (off.back() != end)
+    return set_error(GP_E_BAD_GEOMETRY, "%s ends at %lld, expected %lld", what,
+                     (long long)off.back(), (long long)end);
+  return GP_OK;
+}
+
+// ------------------------------------------------------------------------- grid build
+
+extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
+                                   const gp_grid_params *params, void *hip_stream,
+                                   gp_grid **out) {
+  if (!out || !geom || !params) return set_error(GP_E_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (kind != GP_PIP && kind != GP_P2P) return set_error(GP_E_INVALID_ARG, "bad kind");
+  const double cs = params->cell_size;
+  if (!(cs > 0.0) || !std::isfinite(cs))
+    return set_error(GP_E_INVALID_ARG, "cell_size must be finite and > 0");
+  const double D = kind == GP_P2P ? params->radius_D : 0.0;
+  if (!(D >= 0.0) || !std::isfinite(D))
+    return set_error(GP_E_INVALID_ARG, "radius_D must be finite and >= 0");
+  if (params->nx < 0 || params->ny < 0) return set_error(GP_E_INVALID_ARG, "negative nx/ny");
+  const bool derive = params->nx == 0 || params->ny == 0;
+  if (!derive && (!std::isfinite(params->x0) || !std::isfinite(params->y0)))
+    return set_error(GP_E_INVALID_ARG, "non-finite grid origin");
+  const int64_t nf = geom->n_features, nr = geom->n_rings, nv = geom->n_vertices;
+  if (nf < 0 || nr < 0 || nv < 0) return set_error(GP_E_INVALID_ARG, "negative count");
+  if (nf >= kMaxCount || nr >= kMaxCount || nv >= kMaxCount)
+    return set_error(GP_E_CAPACITY, "counts must stay below 2^31");
+  if (kind == GP_PIP && nf > 0 && !geom->feature_ring_off)
+    return set_error(GP_E_INVALID_ARG, "polygons need feature_ring_off");
+  if (kind == GP_P2P && nr != nf)
+    return set_error(GP_E_INVALID_ARG, "polylines need n_rings == n_features");
+  if (!geom->ring_vert_off || (nv > 0 && (!geom->x || !geom->y)))
+    return set_error(GP_E_INVALID_ARG, "null geometry array");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const bool dev = geom->on_device != 0;
+
+  HostGeom h;
+  GP_TRY_HIP(fetch(h.rvo, geom->ring_vert_off, (size_t)nr + 1, dev));
+  if (kind == GP_PIP) GP_TRY_HIP(fetch(h.fro, geom->feature_ring_off, (size_t)nf + 1, dev));
+  GP_TRY_HIP(fetch(h.x, geom->x, (size_t)nv, dev));
+  GP_TRY_HIP(fetch(h.y, geom->y, (size_t)nv, dev));
+  gp_status st = check_offsets(h.rvo, nv, "ring_vert_off");
+  if (st) return st;
+  if (kind == GP_PIP) {
+    st = check_offsets(h.fro, nr, "feature_ring_off");
+    if (st) return st;
+  } else {
+    for (int64_t f = 0; f < nf; ++f)
+      if (h.rvo[f + 1] - h.rvo[f] < 2)
+        return set_error(GP_E_BAD_GEOMETRY, "polyline %lld has fewer than 2 vertices",
+                         (long long)f);
+  }
+  for (int64_t v = 0; v < nv; ++v)
+    if (!std::isfinite(h.x[v]) || !std::isfinite(h.y[v]))
+      return set_error(GP_E_BAD_GEOMETRY, "vertex %lld is not finite", (long long)v);
+
+  int device = 0;
+  GP_TRY_HIP(hipGetDevice(&device));
+  int num_cu = 0;
+  GP_TRY_HIP(hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, device));
+
+  std::vector<int32_t> rvo32(h.rvo.begin(), h.rvo.end());
+  std::vector<int32_t> fro32(h.fro.begin(), h.fro.end());
+  if (fro32.empty()) fro32.push_back(0);
+  const int64_t nedges = kind == GP_PIP ? nv : nv - nf;
+
+  DevBuf d_rvo, d_fro, d_x, d_y, d_mbb;
+  GP_TRY_HIP(d_rvo.alloc(rvo32.size() * 4));
+  GP_TRY_HIP(d_fro.alloc(fro32.size() * 4));
+  GP_TRY_HIP(d_x.alloc((size_t)nv * 8));
+  GP_TRY_HIP(d_y.alloc((size_t)nv * 8));
+  GP_TRY_HIP(d_mbb.alloc((size_t)std::max<int64_t>(nf, 1) * 32));
+  GP_TRY_HIP(hipMemcpyAsync(d_rvo.p, rvo32.data(), rvo32.size() * 4, hipMemcpyHostToDevice, s));
+  GP_TRY_HIP(hipMemcpyAsync(d_fro.p, fro32.data(), fro32.size() * 4, hipMemcpyHostToDevice, s));
+  if (nv) {
+    GP_TRY_HIP(hipMemcpyAsync(d_x.p, h.x.data(), (size_t)nv * 8, hipMemcpyHostToDevice, s));
+    GP_TRY_HIP(hipMemcpyAsync(d_y.p, h.y.data(), (size_t)nv * 8, hipMemcpyHostToDevice, s));
+  }
+
+  gp_grid *g = new gp_grid();
+  memset((gp::Grid *)g, 0, sizeof(gp::Grid));
+  auto fail = [&](gp_status code) {
+    gp_grid_free(g);
+    return code;
+  };
+  g->kind = kind;
+  g->device = device;
+  g->num_cu = num_cu;
+  g->cs = cs;
+  g->D = D;
+  g->D2 = D * D;
+  g->nf = (int32_t)nf;
+  g->nedges = (int32_t)nedges;
+  g->tune[GP_FP64] = default_tuning(kind, GP_FP64);
+  g->tune[GP_MIXED] = default_tuning(kind, GP_MIXED);
+
+#define GP_TRY_HIP_G(expr)                                                                \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(set_error(GP_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)));    \
+  } while (0)
+
+  GP_TRY_HIP_G(hipMalloc(&g->d_eoff, ((size_t)nf + 1) * 4));
+  GP_TRY_HIP_G(hipMalloc(&g->d_edge64, (size_t)std::max<int64_t>(nedges, 1) * sizeof(double4)));
+  GP_TRY_HIP_G(hipMalloc(&g->d_k32, (size_t)std::max<int64_t>(nedges, 1) * 4));
+  GP_TRY_HIP_G(launch_build_edges(d_rvo.as<int32_t>(), d_fro.as<int32_t>(), d_x.as<double>(),
+                                  d_y.as<double>(), (int32_t)nf, (int32_t)nr, (int32_t)nv, kind,
+                                  g->d_edge64, g->d_k32, g->d_eoff, s));
+  GP_TRY_HIP_G(launch_mbb(d_rvo.as<int32_t>(), d_fro.as<int32_t>(), d_x.as<double>(),
+                          d_y.as<double>(), (int32_t)nf, kind, D, cs, d_mbb.as<double>(), s));
+
+  // extent
+  double x0 = params->x0, y0 = params->y0;
+  int64_t nx = params->nx, ny = params->ny;
+  if (derive) {
+    if (nf == 0) {
+      x0 = 0.0; y0 = 0.0; nx = 1; ny = 1;
+    } else {
+      DevBuf d_ext;
+      GP_TRY_HIP_G(d_ext.alloc(32));
+      GP_TRY_HIP_G(launch_extent(d_mbb.as<double>(), (int32_t)nf, d_ext.as<double>(), s));
+      double ext[4];
+      GP_TRY_HIP_G(hipMemcpyAsync(ext, d_ext.p, 32, hipMemcpyDeviceToHost, s));
+      GP_TRY_HIP_G(hipStreamSynchronize(s));
+      x0 = ext[0];
+      y0 = ext[1];
+      double fx = std::floor((ext[2] - x0) / cs), fy = std::floor((ext[3] - y0) / cs);
+      if (!(fx < (double)kMaxCells && fy < (double)kMaxCells))
+        return fail(set_error(GP_E_CAPACITY, "derived grid is too large"));
+      nx = (int64_t)fx + 1;
+      ny = (int64_t)fy + 1;
+    }
+  }
+  if (nx * ny > kMaxCells || nx > kMaxCells || ny > kMaxCells)
+    return fail(set_error(GP_E_CAPACITY, "grid of %lld x %lld cells exceeds 2^28 cells",
+                          (long long)nx, (long long)ny));
+  g->x0 = x0;
+  g->y0 = y0;
+  g->nx = (int32_t)nx;
+  g->ny = (int32_t)ny;
+  g->ncells = (int32_t)(nx * ny);
+  const int32_t ncells = g->ncells;
+
+  // rasterise the MBBs: per-feature counts, offsets, emit, stable sort by cell
+  {
+    DevBuf d_cnt, d_tmp;
+    const size_t nfe = (size_t)nf + 1;
+    GP_TRY_HIP_G(d_cnt.alloc(nfe * 4));
+    GP_TRY_HIP_G(d_tmp.alloc(scan_tmp_elems(std::max(nfe, (size_t)ncells + 1)) * 4));
+    GP_TRY_HIP_G(launch_raster_count(d_mbb.as<double>(), (int32_t)nf, x0, y0, cs, g->nx, g->ny,
+                                     d_cnt.as<uint32_t>(), s));
+    GP_TRY_HIP_G(launch_exclusive_scan_u32(d_cnt.as<uint32_t>(), d_cnt.as<uint32_t>(), nfe,
+                                           d_tmp.as<uint32_t>(), s));
+    uint32_t npairs = 0;
+    GP_TRY_HIP_G(hipMemcpyAsync(&npairs, d_cnt.as<uint32_t>() + nf, 4, hipMemcpyDeviceToHost, s));
+    GP_TRY_HIP_G(hipStreamSynchronize(s));
+    if (npairs >= (uint32_t)kMaxCount)
+      return fail(set_error(GP_E_CAPACITY, "too many (cell, feature) pairs"));
+    g->npairs = (int32_t)npairs;
+    DevBuf kA, kB, vA, vB, hist, stmp;
+    const size_t np = std::max<size_t>(npairs, 1);
+    GP_TRY_HIP_G(kA.alloc(np * 4));
+    GP_TRY_HIP_G(kB.alloc(np * 4));
+    GP_TRY_HIP_G(vA.alloc(np * 4));
+    GP_TRY_HIP_G(vB.alloc(np * 4));
+    GP_TRY_HIP_G(hist.alloc(radix_hist_elems(np) * 4));
+    GP_TRY_HIP_G(stmp.alloc(scan_tmp_elems(std::max(radix_hist_elems(np), (size_t)ncells + 1)) * 4));
+    GP_TRY_HIP_G(launch_raster_emit(d_mbb.as<double>(), (int32_t)nf, x0, y0, cs, g->nx, g->ny,
+                                    d_cnt.as<uint32_t>(), kA.as<uint32_t>(), vA.as<uint32_t>(), s));
+    uint32_t *skeys = nullptr, *svals = nullptr;
+    GP_TRY_HIP_G(launch_radix_sort(kA.as<uint32_t>(), kB.as<uint32_t>(), vA.as<uint32_t>(),
+                                   vB.as<uint32_t>(), npairs, bits_for((uint64_t)ncells - 1),
+                                   false, hist.as<uint32_t>(), stmp.as<uint32_t>(), s, &skeys,
+                                   &svals));
+    GP_TRY_HIP_G(hipMalloc(&g->d_cand_off, ((size_t)ncells + 1) * 4));
+    GP_TRY_HIP_G(hipMalloc(&g->d_cand_id, np * 4));
+    GP_TRY_HIP_G(hipMalloc(&g->d_cell_edges, std::max<size_t>(ncells, 1) * 8));
+    GP_TRY_HIP_G(launch_fill_u32((uint32_t *)g->d_cand_off, 0u, (size_t)ncells + 1, s));
+    GP_TRY_HIP_G(launch_histogram(skeys, npairs, (uint32_t *)g->d_cand_off, s));
+    GP_TRY_HIP_G(launch_exclusive_scan_u32((uint32_t *)g->d_cand_off, (uint32_t *)g->d_cand_off,
+                                           (size_t)ncells + 1, stmp.as<uint32_t>(), s));
+    if (npairs)
+      GP_TRY_HIP_G(hipMemcpyAsync(g->d_cand_id, svals, (size_t)npairs * 4,
+                                  hipMemcpyDeviceToDevice, s));
+    GP_TRY_HIP_G(launch_cell_edges(g->d_cand_off, g->d_cand_id, g->d_eoff, ncells,
+                                   g->d_cell_edges, s));
+    GP_TRY_HIP_G(hipStreamSynchronize(s));
+  }
+#undef GP_TRY_HIP_G
+  *out = g;
+  return GP_OK;
+}
+
+extern "C" void gp_grid_free(gp_grid *g) {
+  if (!g) return;
+  (void)hipFree(g->d_eoff);
+  (void)hipFree(g->d_edge64);
+  (void)hipFree(g->d_k32);
+  (void)hipFree(g->d_cand_off);
+  (void)hipFree(g->d_cand_id);
+  (void)hipFree(g->d_cell_edges);
+  delete g;
+}
+
+extern "C" gp_status gp_grid_get_info(const gp_grid *g, gp_grid_info *info) {
+  if (!g || !info) return set_error(GP_E_INVALID_ARG, "null argument");
+  info->kind = g->kind;
+  info->x0 = g->x0;
+  info->y0 = g->y0;
+  info->cell_size = g->cs;
+  info->radius_D = g->D;
+  info->nx = g->nx;
+  info->ny = g->ny;
+  info->n_features = g->nf;
+  info->n_edges = g->nedges;
+  info->n_pairs = g->npairs;
+  return GP_OK;
+}
+
+extern "C" gp_status gp_grid_candidates(const gp_grid *g, int32_t *cand_off, int32_t *cand_id) {
+  if (!g || !cand_off || (!cand_id && g->npairs)) return set_error(GP_E_INVALID_ARG, "null argument");
+  GP_TRY_HIP(hipMemcpy(cand_off, g->d_cand_off, ((size_t)g->ncells + 1) * 4, hipMemcpyDeviceToHost));
+  if (g->npairs)
+    GP_TRY_HIP(hipMemcpy(cand_id, g->d_cand_id, (size_t)g->npairs * 4, hipMemcpyDeviceToHost));
+  return GP_OK;
+}
+
+// ------------------------------------------------------------------------- workspace
+
+static int64_t max_items(const Grid &g, int64_t n) {
+  return n / 64 + std::min<int64_t>(g.ncells, n) + 1;
+}
+
+namespace gp {
+size_t workspace_layout(const Grid &g, int64_t n, gp_precision prec, void *base, Workspace *ws) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void * {
+    size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 16), 256);
+    return base ? (void *)((char *)base + o) : nullptr;
+  };
+  const size_t un = (size_t)std::max<int64_t>(n, 1);
+  const size_t hist = radix_hist_elems(un);
+  const size_t nc1 = (size_t)g.ncells + 1;
+  Workspace w;
+  w.keyA = (uint32_t *)take(un * 4);
+  w.keyB = (uint32_t *)take(un * 4);
+  w.valA = (uint32_t *)take(un * 4);
+  w.valB = (uint32_t *)take(un * 4);
+  w.hist = (uint32_t *)take(hist * 4);
+  w.scan_tmp = (uint32_t *)take(scan_tmp_elems(std::max(hist, nc1)) * 4);
+  w.pt_off = (int32_t *)take(nc1 * 4);
+  w.item_cnt = (uint32_t *)take(nc1 * 4);
+  w.items = (Item *)take((size_t)max_items(g, n) * sizeof(Item));
+  w.counters = (uint32_t *)take(C_COUNT * 4);
+  w.tests = (unsigned long long *)take(16);
+  if (prec == GP_MIXED) {
+    w.xs32 = (float *)take(un * 4);
+    w.ys32 = (float *)take(un * 4);
+    w.xs64 = w.ys64 = nullptr;
+    w.rq = (uint32_t *)take(un * 4);
+  } else {
+    w.xs32 = w.ys32 = nullptr;
+    w.xs64 = (double *)take(un * 8);
+    w.ys64 = (double *)take(un * 8);
+    w.rq = nullptr;
+  }
+  w.bytes = off;
+  if (ws) *ws = w;
+  return off;
+}
+}  // namespace gp
+
+extern "C" gp_status gp_workspace_bytes(const gp_grid *g, int64_t n, gp_precision prec,
+                                        size_t *bytes) {
+  if (!g || !bytes) return set_error(GP_E_INVALID_ARG, "null argument");
+  if (n < 0 || n >= kMaxCount) return set_error(GP_E_CAPACITY, "n must be in [0, 2^31)");
+  if (prec != GP_FP64 && prec != GP_MIXED) return set_error(GP_E_INVALID_ARG, "bad precision");
+  *bytes = workspace_layout(*g, n, prec, nullptr, nullptr);
+  return GP_OK;
+}
+
+// ------------------------------------------------------------------------- queries
+
+namespace gp {
+
+struct QueryPlan {
+  RefineArgs a;
+  Workspace w;
+  uint32_t *perm;
+  int32_t nbits;
+};
+
+static float half_box(const Grid &g) {
+  double hb = 0.5 * g.cs * (1.0 + 0x1p-18) +
+              0x1p-48 * (std::fabs(g.x0) + std::fabs(g.y0) + g.cs * (double)(g.nx + g.ny));
+  return (float)(hb * (1.0 + 0x1p-20));
+}
+
+// Hash, sort and offsets: the point side of the filter.
+static hipError_t pair_points(const Grid &g, int64_t n, const double *px, const double *py,
+                              Workspace &w, hipStream_t s, uint32_t **skey, uint32_t **perm) {
+  hipError_t e = launch_hash(px, py, n, g.x0, g.y0, g.cs, g.nx, g.ny, w.keyA, s);
+  if (e != hipSuccess) return e;
+  e = launch_radix_sort(w.keyA, w.keyB, w.valA, w.valB, (size_t)n, bits_for((uint64_t)g.ncells),
+                        true, w.hist, w.scan_tmp, s, skey, perm);
+  if (e != hipSuccess) return e;
+  return launch_offsets(*skey, n, g.ncells, w.pt_off, s);
+}
+
+static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const double *px,
+                           const double *py, int32_t *out_id, double *out_dist,
+                           gp_precision prec, void *ws, size_t ws_bytes, hipStream_t s,
+                           gp_stats *stats, const gp_tuning *override_tuning) {
+  if (!g) return set_error(GP_E_INVALID_ARG, "null grid");
+  if (g->kind != kind)
+    return set_error(GP_E_INVALID_ARG, "grid was built for the other operation");
+  if (prec != GP_FP64 && prec != GP_MIXED) return set_error(GP_E_INVALID_ARG, "bad precision");
+  if (n < 0 || n >= kMaxCount) return set_error(GP_E_CAPACITY, "n must be in [0, 2^31)");
+  if (stats) memset(stats, 0, sizeof(*stats));
+  if (n == 0) return GP_OK;
+  if (!px || !py || !out_id || (kind == GP_P2P && !out_dist))
+    return set_error(GP_E_INVALID_ARG, "null point or output pointer");
+  Workspace w;
+  const size_t need = workspace_layout(*g, n, prec, ws, &w);
+  if (!ws || ws_bytes < need)
+    return set_error(GP_E_INVALID_ARG, "workspace too small: %zu bytes needed", need);
+  const gp_tuning t = override_tuning ? *override_tuning : g->tune[prec];
+  if (!tuning_valid(t)) return set_error(GP_E_INVALID_ARG, "invalid tuning");
+
+  hipEvent_t ev[5] = {};
+  if (stats) {
+    for (auto &e : ev) GP_TRY_HIP(hipEventCreate(&e));
+    GP_TRY_HIP(hipEventRecord(ev[0], s));
+  }
+  GP_TRY_HIP(launch_fill_u32(w.counters, 0u, C_COUNT, s));
+  GP_TRY_HIP(launch_fill_u32((uint32_t *)w.tests, 0u, 2, s));
+  uint32_t *skey = nullptr, *perm = nullptr;
+  GP_TRY_HIP(pair_points(*g, n, px, py, w, s, &skey, &perm));
+
+  RefineArgs a;
+  memset(&a, 0, sizeof(a));
+  a.items = w.items;
+  a.n_items = w.item_cnt + g->ncells;
+  a.item_counter = w.counters + C_ITEM;
+  a.cand_off = g->d_cand_off;
+  a.cand_id = g->d_cand_id;
+  a.eoff = g->d_eoff;
+  a.edge64 = g->d_edge64;
+  a.k32 = g->d_k32;
+  a.x0 = g->x0;
+  a.y0 = g->y0;
+  a.cs = g->cs;
+  a.nx = g->nx;
+  a.ncells = g->ncells;
+  a.D = g->D;
+  a.D2 = g->D2;
+  a.D2_next = std::nextafter(g->D2, INFINITY);
+  a.half_box = half_box(*g);
+  a.p2p_margin = (float)std::max(0.01 * g->D, g->cs * 0x1p-10);
+  a.skey = skey;
+  a.perm = perm;
+  a.xs32 = w.xs32;
+  a.ys32 = w.ys32;
+  a.xs64 = w.xs64;
+  a.ys64 = w.ys64;
+  a.px = px;
+  a.py = py;
+  a.out_id = out_id;
+  a.out_dist = kind == GP_P2P ? out_dist : nullptr;
+  a.rq = w.rq;
+  a.rq_count = w.counters + C_RQ;
+  a.edge_chunk = t.edge_chunk;
+
+  GP_TRY_HIP(launch_gather(a, n, prec == GP_MIXED, w.counters + C_NPAIRED, w.xs32, w.ys32,
+                           w.xs64, w.ys64, s));
+  GP_TRY_HIP(launch_items(w.pt_off, g->d_cand_off, g->d_cell_edges, g->ncells,
+                          64 * t.points_per_lane, w.item_cnt, w.scan_tmp, w.items, w.counters,
+                          w.tests, s));
+  if (stats) GP_TRY_HIP(hipEventRecord(ev[1], s));
+  const int64_t mi = n / (64 * t.points_per_lane) + std::min<int64_t>(g->ncells, n) + 1;
+  GP_TRY_HIP(launch_refine(kind, prec, a, t, g->num_cu, mi, s));
+  if (stats) GP_TRY_HIP(hipEventRecord(ev[2], s));
+  if (prec == GP_MIXED) GP_TRY_HIP(launch_recheck(kind, a, g->num_cu, s));
+  if (stats) {
+    GP_TRY_HIP(hipEventRecord(ev[3], s));
+    GP_TRY_HIP(hipEventSynchronize(ev[3]));
+    uint32_t cnt[C_COUNT];
+    unsigned long long tests = 0;
+    uint32_t nitems = 0;
+    GP_TRY_HIP(hipMemcpy(cnt, w.counters, sizeof(cnt), hipMemcpyDeviceToHost));
+    GP_TRY_HIP(hipMemcpy(&tests, w.tests, 8, hipMemcpyDeviceToHost));
+    GP_TRY_HIP(hipMemcpy(&nitems, a.n_items, 4, hipMemcpyDeviceToHost));
+    float m01 = 0, m12 = 0, m23 = 0, m03 = 0;
+    GP_TRY_HIP(hipEventElapsedTime(&m01, ev[0], ev[1]));
+    GP_TRY_HIP(hipEventElapsedTime(&m12, ev[1], ev[2]));
+    GP_TRY_HIP(hipEventElapsedTime(&m23, ev[2], ev[3]));
+    GP_TRY_HIP(hipEventElapsedTime(&m03, ev[0], ev[3]));
+    stats->n_points = n;
+    stats->n_paired = cnt[C_NPAIRED];
+    stats->n_items = nitems;
+    stats->tests = tests;
+    stats->n_rechecked = prec == GP_MIXED ? cnt[C_RQ] : 0;
+    stats->ms_pairing = m01;
+    stats->ms_refine = m12;
+    stats->ms_recheck = m23;
+    stats->ms_total = m03;
+    for (auto &e : ev) (void)hipEventDestroy(e);
+  }
+  return GP_OK;
+}
+
+gp_status run_query_tuned(const gp_grid *g, gp_kind kind, int64_t n, const double *px,
+                          const double *py, int32_t *out_id, double *out_dist,
+                          gp_precision prec, void *ws, size_t ws_bytes, hipStream_t s,
+                          gp_stats *stats, const gp_tuning *t) {
+  return run_query(g, kind, n, px, py, out_id, out_dist, prec, ws, ws_bytes, s, stats, t);
+}
+
+}  // namespace gp
+
+extern "C" gp_status gp_pair_points(const gp_grid *g, int64_t n, const double *px,
+                                    const double *py, int32_t *perm_out, int32_t *pt_off_out,
+                                    void *ws, size_t ws_bytes, void *hip_stream) {
+  if (!g) return set_error(GP_E_INVALID_ARG, "null grid");
+  if (n < 0 || n >= kMaxCount) return set_error(GP_E_CAPACITY, "n must be in [0, 2^31)");
+  if (!pt_off_out || (n > 0 && (!px || !py || !perm_out)))
+    return set_error(GP_E_INVALID_ARG, "null pointer");
+  Workspace w;
+  const size_t need = workspace_layout(*g, n, GP_FP64, ws, &w);
+  if (!ws || ws_bytes < need)
+    return set_error(GP_E_INVALID_ARG, "workspace too small: %zu bytes needed", need);
+  hipStream_t s = (hipStream_t)hip_stream;
+  uint32_t *skey = w.keyA, *perm = w.valA;
+  if (n > 0) GP_TRY_HIP(pair_points(*g, n, px, py, w, s, &skey, &perm));
+  else GP_TRY_HIP(launch_offsets(skey, 0, g->ncells, w.pt_off, s));
+  GP_TRY_HIP(launch_copy_perm(perm, n, perm_out, s));
+  GP_TRY_HIP(hipMemcpyAsync(pt_off_out, w.pt_off, ((size_t)g->ncells + 1) * 4,
+                            hipMemcpyDeviceToDevice, s));
+  return GP_OK;
+}
+
+extern "C" gp_status gp_pip(const gp_grid *g, int64_t n, const double *px, const double *py,
+                            int32_t *out_id, gp_precision prec, void *ws, size_t ws_bytes,
+                            void *hip_stream, gp_stats *stats) {
+  return run_query(g, GP_PIP, n, px, py, out_id, nullptr, prec, ws, ws_bytes,
+                   (hipStream_t)hip_stream, stats, nullptr);
+}
+
+extern "C" gp_status gp_p2p(const gp_grid *g, int64_t n, const double *px, const double *py,
+                            int32_t *out_id, double *out_dist, gp_precision prec, void *ws,
+                            size_t ws_bytes, void *hip_stream, gp_stats *stats) {
+  return run_query(g, GP_P2P, n, px, py, out_id, out_dist, prec, ws, ws_bytes,
+                   (hipStream_t)hip_stream, stats, nullptr);
+}
+
+// ------------------------------------------------------------------------- tuning
+
+extern "C" gp_status gp_set_tuning(gp_grid *g, gp_precision prec, const gp_tuning *t) {
+  if (!g || !t) return set_error(GP_E_INVALID_ARG, "null argument");
+  if (prec != GP_FP64 && prec != GP_MIXED) return set_error(GP_E_INVALID_ARG, "bad precision");
+  gp_tuning v = *t;
+  gp_tuning d = default_tuning(g->kind, prec);
+  if (v.points_per_lane == 0) v.points_per_lane = d.points_per_lane;
+  if (v.edge_chunk == 0) v.edge_chunk = d.edge_chunk;
+  if (v.wg_per_cu == 0) v.wg_per_cu = d.wg_per_cu;
+  if (!tuning_valid(v)) return set_error(GP_E_INVALID_ARG, "invalid tuning");
+  g->tune[prec] = v;
+  return GP_OK;
+}
+
+extern "C" gp_status gp_get_tuning(const gp_grid *g, gp_precision prec, gp_tuning *t) {
+  if (!g || !t) return set_error(GP_E_INVALID_ARG, "null argument");
+  if (prec != GP_FP64 && prec != GP_MIXED) return set_error(GP_E_INVALID_ARG, "bad precision");
+  *t = g->tune[prec];
+  return GP_OK;
+}
+
+// Grid search over points per lane, LDS edge chunk, persistent workgroups per CU and the
+// queue mode; each configuration is timed (median of 3 after one warm-up) on the sample.
+extern "C" gp_status gp_autotune(gp_grid *g, gp_precision prec, int64_t n, const double *px,
+                                 const double *py, void *ws, size_t ws_bytes, void *hip_stream,
+                                 gp_tuning *best, float *best_ms) {
+  if (!g) return set_error(GP_E_INVALID_ARG, "null grid");
+  if (prec != GP_FP64 && prec != GP_MIXED) return set_error(GP_E_INVALID_ARG, "bad precision");
+  if (n <= 0) return set_error(GP_E_INVALID_ARG, "autotune needs sample points");
+  hipStream_t s = (hipStream_t)hip_stream;
+  DevBuf d_id, d_dist;
+  GP_TRY_HIP(d_id.alloc((size_t)n * 4));
+  GP_TRY_HIP(d_dist.alloc((size_t)n * 8));
+  std::vector<gp_tuning> space;
+  const int ppls[3] = {1, 2, 4}, ecs[3] = {128, 256, 512}, wgs[3] = {4, 8, 16};
+  for (int p : ppls)
+    for (int e : ecs)
+      for (int wgc : wgs) space.push_back(gp_tuning{p, e, wgc, 1});
+  for (int p : ppls) space.push_back(gp_tuning{p, 256, 8, 0});
+  float best_t = INFINITY;
+  gp_tuning best_cfg = g->tune[prec];
+  for (const gp_tuning &t : space) {
+    float times[3];
+    for (int r = 0; r < 4; ++r) {
+      gp_stats st;
+      gp_status rc = run_query(g, g->kind, n, px, py, d_id.as<int32_t>(), d_dist.as<double>(),
+                               prec, ws, ws_bytes, s, &st, &t);
+      if (rc) return rc;
+      if (r > 0) times[r - 1] = st.ms_total;
+    }
+    std::sort(times, times + 3);
+    if (times[1] < best_t) {
+      best_t = times[1];
+      best_cfg = t;
+    }
+  }
+  g->tune[prec] = best_cfg;
+  if (best) *best = best_cfg;
+  if (best_ms) *best_ms = best_t;
+  return GP_OK;
+}

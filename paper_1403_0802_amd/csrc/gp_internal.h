@@ -1,0 +1,139 @@
+// Internal interface between the host runtime (gp_api.cpp, gp_serve.cpp) and the HIP
+// kernels (gp_kernels.hip).  Not installed; the public ABI is include/gp.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/gp.h"
+
+namespace gp {
+
+// Work item of the refinement: a grid cell and a chunk of its (sorted) points.  The
+// cell's whole candidate list is refined by one workgroup, so per-point results never
+// need a cross-workgroup merge.
+struct Item {
+  int32_t cell;
+  int32_t pt_lo;
+  int32_t npts;
+  int32_t cost_rank;  // spare: cost bucket used to order the queue
+};
+
+// Everything the refinement kernels read.  Passed by value as the kernel argument.
+struct RefineArgs {
+  // work queue
+  const Item *items;
+  const uint32_t *n_items;   // device scalar written by the item builder
+  uint32_t *item_counter;    // device scalar, zeroed before the launch
+  // grid
+  const int32_t *cand_off;   // [ncells+1]
+  const int32_t *cand_id;    // [npairs]
+  const int32_t *eoff;       // [nf+1] edge (PIP) or segment (P2P) range of a feature
+  const double4 *edge64;     // PIP: (lo.x, lo.y, hi.x, hi.y); P2P: (a.x, a.y, b.x, b.y)
+  const float *k32;          // PIP: fl32(w/h), 0 for horizontal edges
+  double x0, y0, cs;
+  int32_t nx, ncells;
+  double D, D2, D2_next;     // P2P: D, fl(D*D), the smallest double above fl(D*D)
+  float half_box;            // bound on |rebased point coordinate| inside its cell
+  float p2p_margin;          // P2P: T, the "near the cell" margin (distance units)
+  // points, sorted by cell
+  const uint32_t *skey;      // sorted cell ids
+  const uint32_t *perm;      // sorted position -> caller index
+  const float *xs32, *ys32;  // GP_MIXED: rebased FP32
+  const double *xs64, *ys64; // GP_FP64: sorted FP64
+  const double *px, *py;     // caller's points (recheck reads them through perm)
+  // outputs (caller order)
+  int32_t *out_id;
+  double *out_dist;
+  // FP64 recheck queue (sorted positions)
+  uint32_t *rq;
+  uint32_t *rq_count;
+  int32_t edge_chunk;
+};
+
+// Device-resident grid.
+struct Grid {
+  gp_kind kind;
+  int device;
+  double x0, y0, cs, D, D2;
+  int32_t nx, ny, ncells;
+  int32_t nf, nedges, npairs;
+  int32_t *d_eoff;
+  double4 *d_edge64;
+  float *d_k32;
+  int32_t *d_cand_off;
+  int32_t *d_cand_id;
+  int64_t *d_cell_edges;  // [ncells] sum of nedges over the cell's candidates
+  gp_tuning tune[2];
+  int num_cu;
+};
+
+// Workspace layout for n points.
+struct Workspace {
+  uint32_t *keyA, *keyB, *valA, *valB;
+  uint32_t *hist;        // radix histogram [256 * nblk]
+  uint32_t *scan_tmp;    // scan partials
+  int32_t *pt_off;       // [ncells+1]
+  float *xs32, *ys32;
+  double *xs64, *ys64;
+  uint32_t *item_cnt;    // [ncells+1] -> exclusive offsets
+  Item *items;
+  uint32_t *rq;
+  uint32_t *counters;    // [16]: 0 item counter, 1 rq count, 2 n_items(copy), ...
+  unsigned long long *tests;  // [1]
+  size_t bytes;
+};
+
+enum Counter { C_ITEM = 0, C_RQ = 1, C_NITEMS = 2, C_NPAIRED = 3, C_COUNT = 16 };
+
+size_t workspace_layout(const Grid &g, int64_t n, gp_precision prec, void *base, Workspace *ws);
+size_t scan_tmp_elems(size_t n);
+
+// ---- launchers (gp_kernels.hip); all enqueue on `s` and return hipGetLastError()
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t n,
+                                     uint32_t *tmp, hipStream_t s);
+hipError_t launch_radix_sort(uint32_t *keyA, uint32_t *keyB, uint32_t *valA, uint32_t *valB,
+                             size_t n, int nbits, bool values_are_identity, uint32_t *hist,
+                             uint32_t *scan_tmp, hipStream_t s, uint32_t **keys_out,
+                             uint32_t **vals_out);
+size_t radix_hist_elems(size_t n);
+
+// grid build
+hipError_t launch_build_edges(const int32_t *ring_vert_off, const int32_t *feature_ring_off,
+                              const double *x, const double *y, int32_t nf, int32_t nrings,
+                              int32_t nverts, gp_kind kind, double4 *edge64, float *k32,
+                              int32_t *eoff, hipStream_t s);
+hipError_t launch_mbb(const int32_t *ring_vert_off, const int32_t *feature_ring_off,
+                      const double *x, const double *y, int32_t nf, gp_kind kind, double D,
+                      double cs, double *mbb, hipStream_t s);
+hipError_t launch_extent(const double *mbb, int32_t nf, double *out4, hipStream_t s);
+hipError_t launch_raster_count(const double *mbb, int32_t nf, double x0, double y0, double cs,
+                               int32_t nx, int32_t ny, uint32_t *cnt, hipStream_t s);
+hipError_t launch_raster_emit(const double *mbb, int32_t nf, double x0, double y0, double cs,
+                              int32_t nx, int32_t ny, const uint32_t *off, uint32_t *pair_cell,
+                              uint32_t *pair_fid, hipStream_t s);
+hipError_t launch_histogram(const uint32_t *keys, size_t n, uint32_t *cnt, hipStream_t s);
+hipError_t launch_cell_edges(const int32_t *cand_off, const int32_t *cand_id,
+                             const int32_t *eoff, int32_t ncells, int64_t *cell_edges,
+                             hipStream_t s);
+
+// query pipeline
+hipError_t launch_hash(const double *px, const double *py, int64_t n, double x0, double y0,
+                       double cs, int32_t nx, int32_t ny, uint32_t *key, hipStream_t s);
+hipError_t launch_offsets(const uint32_t *skey, int64_t n, int32_t ncells, int32_t *pt_off,
+                          hipStream_t s);
+hipError_t launch_gather(const RefineArgs &a, int64_t n, bool mixed, uint32_t *n_paired,
+                         float *xs32, float *ys32, double *xs64, double *ys64,
+                         hipStream_t s);
+hipError_t launch_items(const int32_t *pt_off, const int32_t *cand_off,
+                        const int64_t *cell_edges, int32_t ncells, int32_t chunk,
+                        uint32_t *item_cnt, uint32_t *scan_tmp, Item *items, uint32_t *counters,
+                        unsigned long long *tests, hipStream_t s);
+hipError_t launch_refine(gp_kind kind, gp_precision prec, const RefineArgs &a,
+                         const gp_tuning &t, int num_cu, int64_t max_items, hipStream_t s);
+hipError_t launch_recheck(gp_kind kind, const RefineArgs &a, int num_cu, hipStream_t s);
+hipError_t launch_copy_perm(const uint32_t *perm, int64_t n, int32_t *out, hipStream_t s);
+
+}  // namespace gp

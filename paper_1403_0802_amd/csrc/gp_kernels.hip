@@ -1,0 +1,1232 @@
+// HIP kernels for gfx950 (MI355X): grid pairing and PIP / P2P refinement.
+//
+// Paper: Zhang & You, arXiv 1403.0802.  Sec. III.A (grid filter built from sorts,
+// scans and MBB rasterisation), Sec. III.B (P2P: a (cell, {polyline}) pair per thread
+// block, a point per thread, looping over the polylines' vertices; Fig. 2 distance
+// cases), Sec. III.C (PIP: same mapping, ray crossing over every ring, Fig. 3).
+//
+// MI355X mapping.  A work item is one grid cell plus a chunk of up to 64*PPL of its
+// points; one 64-lane wavefront owns the item, holds PPL points per lane in VGPRs, and
+// walks the cell's whole candidate list in ascending feature id, staging each
+// feature's edges through LDS in chunks (every lane then reads the same LDS word, a
+// broadcast).  Because a single wave sees all candidates of its points, results need
+// no cross-workgroup merge and ties resolve to the smallest id by visiting order.
+// Items are pulled from a device-side queue by a persistent grid sized to the CUs.
+//
+// Compiled with -ffp-contract=off: every FP64 expression is evaluated exactly as
+// written (no fused multiply-add), which is what makes the FP64 forms bitwise
+// reproducible against a scalar FP64 implementation.  The FP32 forms request fused
+// multiply-adds explicitly with fmaf().
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "gp_internal.h"
+
+namespace gp {
+
+#define GP_WAVE 64
+#define SCAN_THREADS 256
+#define SCAN_ITEMS 16
+#define SCAN_TILE (SCAN_THREADS * SCAN_ITEMS)
+#define RS_THREADS 256
+#define RS_ITEMS 16
+#define RS_TILE (RS_THREADS * RS_ITEMS)
+#define RS_BITS 8
+#define RS_BUCKETS 256
+
+__device__ __forceinline__ uint64_t ballot(bool c) { return __ballot(c); }
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  return (1ull << lane_id()) - 1ull;
+}
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+static inline unsigned grid_for(size_t n, unsigned threads, unsigned cap = 65535u * 16u) {
+  size_t g = (n + threads - 1) / threads;
+  if (g == 0) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+// ------------------------------------------------------------------------- fill
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------- scan
+// Exclusive prefix sum of uint32 in three phases (tile reduce, scan of tile sums,
+// tile scan + offset), recursive over the tile sums.  Deterministic.
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < GP_WAVE; off <<= 1) {
+    uint32_t u = __shfl_up(v, off, GP_WAVE);
+    if (lane >= (uint32_t)off) v += u;
+  }
+  return v;
+}
+
+// Block-wide exclusive scan of one value per thread (256 threads); returns the block
+// total through *total.
+__device__ uint32_t block_excl_scan(uint32_t v, uint32_t *total) {
+  __shared__ uint32_t wsum[SCAN_THREADS / GP_WAVE];
+  const uint32_t lane = lane_id(), wave = threadIdx.x / GP_WAVE;
+  uint32_t inc = wave_incl_scan(v);
+  if (lane == GP_WAVE - 1) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < SCAN_THREADS / GP_WAVE; ++w) {
+    uint32_t x = wsum[w];
+    if (w < (int)wave) base += x;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - v;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t *in, size_t n,
+                                                              uint32_t *sums) {
+  const size_t base = (size_t)blockIdx.x * SCAN_TILE;
+  uint32_t acc = 0;
+  for (int r = 0; r < SCAN_ITEMS; ++r) {
+    size_t i = base + (size_t)r * SCAN_THREADS + threadIdx.x;
+    if (i < n) acc += in[i];
+  }
+  uint32_t tot;
+  block_excl_scan(acc, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t *in, uint32_t *out,
+                                                             size_t n, const uint32_t *offs) {
+  __shared__ uint32_t tile[SCAN_TILE + SCAN_TILE / 32];
+  const size_t base = (size_t)blockIdx.x * SCAN_TILE;
+  for (int r = 0; r < SCAN_ITEMS; ++r) {
+    int li = r * SCAN_THREADS + threadIdx.x;
+    size_t i = base + li;
+    tile[li + li / 32] = i < n ? in[i] : 0u;
+  }
+  __syncthreads();
+  uint32_t loc[SCAN_ITEMS];
+  uint32_t acc = 0;
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    int li = threadIdx.x * SCAN_ITEMS + k;
+    loc[k] = tile[li + li / 32];
+    acc += loc[k];
+  }
+  uint32_t tot;
+  uint32_t pre = block_excl_scan(acc, &tot) + (offs ? offs[blockIdx.x] : 0u);
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    int li = threadIdx.x * SCAN_ITEMS + k;
+    tile[li + li / 32] = pre;
+    pre += loc[k];
+  }
+  __syncthreads();
+  for (int r = 0; r < SCAN_ITEMS; ++r) {
+    int li = r * SCAN_THREADS + threadIdx.x;
+    size_t i = base + li;
+    if (i < n) out[i] = tile[li + li / 32];
+  }
+}
+
+size_t scan_tmp_elems(size_t n) {
+  size_t total = 0;
+  while (n > SCAN_TILE) {
+    n = (n + SCAN_TILE - 1) / SCAN_TILE;
+    total += n + 64;
+  }
+  return total + 64;
+}
+
+hipError_t launch_exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t n, uint32_t *tmp,
+                                     hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (n <= SCAN_TILE) {
+    hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(SCAN_THREADS), 0, s, in, out, n,
+                       (const uint32_t *)nullptr);
+    return hipGetLastError();
+  }
+  size_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+  uint32_t *sums = tmp;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, in, n, sums);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_exclusive_scan_u32(sums, sums, nb, tmp + nb + 64, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, in, out, n,
+                     (const uint32_t *)sums);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------- radix sort
+// Stable LSD radix sort of (uint32 key, uint32 value) pairs, 8 bits per pass.  Each
+// pass: per-tile digit histogram, exclusive scan of the digit-major histogram, then a
+// stable scatter in which every key's rank among equal digits of its tile comes from
+// wavefront ballots (peer masks), not from atomics, so the output order is fixed.
+
+size_t radix_hist_elems(size_t n) {
+  size_t nblk = (n + RS_TILE - 1) / RS_TILE;
+  if (nblk == 0) nblk = 1;
+  return (size_t)RS_BUCKETS * nblk;
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t *keys, size_t n,
+                                                        int shift, uint32_t *hist,
+                                                        uint32_t nblk) {
+  __shared__ uint32_t cnt[RS_BUCKETS];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const size_t base = (size_t)blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    size_t i = base + (size_t)r * RS_THREADS + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (RS_BUCKETS - 1)], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t *kin, const uint32_t *vin,
+                                                           uint32_t *kout, uint32_t *vout,
+                                                           size_t n, int shift,
+                                                           const uint32_t *offs, uint32_t nblk) {
+  __shared__ uint32_t run[RS_BUCKETS];
+  __shared__ uint32_t wcnt[RS_THREADS / GP_WAVE][RS_BUCKETS];
+  const uint32_t tid = threadIdx.x, wave = tid / GP_WAVE;
+  run[tid] = offs[(size_t)tid * nblk + blockIdx.x];
+  for (int w = 0; w < RS_THREADS / GP_WAVE; ++w) wcnt[w][tid] = 0;
+  __syncthreads();
+  const size_t base = (size_t)blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    size_t i = base + (size_t)r * RS_THREADS + tid;
+    bool valid = i < n;
+    uint32_t k = valid ? kin[i] : 0u;
+    uint32_t v = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
+    uint32_t d = (k >> shift) & (RS_BUCKETS - 1);
+    uint64_t peers = ballot(valid);
+#pragma unroll
+    for (int b = 0; b < RS_BITS; ++b) {
+      uint64_t m = ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? m : ~m;
+    }
+    uint32_t rank = __popcll(peers & lanemask_lt());
+    if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank;
+      for (uint32_t w = 0; w < wave; ++w) pos += wcnt[w][d];
+      kout[pos] = k;
+      vout[pos] = v;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < RS_THREADS / GP_WAVE; ++w) {
+      add += wcnt[w][tid];
+      wcnt[w][tid] = 0;
+    }
+    run[tid] += add;
+    __syncthreads();
+  }
+}
+
+hipError_t launch_radix_sort(uint32_t *keyA, uint32_t *keyB, uint32_t *valA, uint32_t *valB,
+                             size_t n, int nbits, bool values_are_identity, uint32_t *hist,
+                             uint32_t *scan_tmp, hipStream_t s, uint32_t **keys_out,
+                             uint32_t **vals_out) {
+  *keys_out = keyA;
+  *vals_out = valA;
+  if (n == 0) return hipSuccess;
+  uint32_t nblk = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
+  int passes = (nbits + RS_BITS - 1) / RS_BITS;
+  if (passes < 1) passes = 1;
+  uint32_t *ki = keyA, *ko = keyB, *vi = valA, *vo = valB;
+  bool ident = values_are_identity;
+  for (int p = 0; p < passes; ++p) {
+    int shift = p * RS_BITS;
+    hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(RS_THREADS), 0, s, ki, n, shift, hist, nblk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_exclusive_scan_u32(hist, hist, (size_t)RS_BUCKETS * nblk, scan_tmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(RS_THREADS), 0, s, ki,
+                       ident ? (const uint32_t *)nullptr : vi, ko, vo, n, shift, hist, nblk);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ident = false;
+    uint32_t *t = ki; ki = ko; ko = t;
+    t = vi; vi = vo; vo = t;
+  }
+  *keys_out = ki;
+  *vals_out = vi;
+  return hipSuccess;
+}
+
+// ------------------------------------------------------------------------- grid build
+
+__device__ __forceinline__ int32_t upper_bound_i32(const int32_t *a, int32_t n, int32_t v) {
+  int32_t lo = 0, hi = n;  // first index with a[i] > v
+  while (lo < hi) {
+    int32_t mid = (lo + hi) >> 1;
+    if (a[mid] > v) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+// PIP: edge e = ring vertex e and its successor in the ring (the closing edge wraps).
+// Stored as (lo.x, lo.y, hi.x, hi.y) with lo the endpoint of smaller y (for equal y the
+// successor is lo, which is immaterial: such an edge never crosses) and the FP32 slope
+// k = fl32((hi.x-lo.x)/(hi.y-lo.y)) used by the mixed form.
+// P2P: segment s of polyline f joins vertices v and v+1, s = v - f.
+__global__ void k_build_edges(const int32_t *rvo, const int32_t *fro, const double *x,
+                              const double *y, int32_t nf, int32_t nrings, int32_t nverts,
+                              int kind, double4 *edge64, float *k32, int32_t *eoff) {
+  const int32_t stride = gridDim.x * blockDim.x;
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nverts; v += stride) {
+    int32_t r = upper_bound_i32(rvo, nrings + 1, v) - 1;
+    int32_t r0 = rvo[r], r1 = rvo[r + 1];
+    if (kind == GP_PIP) {
+      int32_t nx = (v + 1 < r1) ? v + 1 : r0;
+      double ax = x[v], ay = y[v], bx = x[nx], by = y[nx];
+      double lox, loy, hix, hiy;
+      if (ay < by) { lox = ax; loy = ay; hix = bx; hiy = by; }
+      else { lox = bx; loy = by; hix = ax; hiy = ay; }
+      edge64[v] = make_double4(lox, loy, hix, hiy);
+      k32[v] = (hiy == loy) ? 0.0f : (float)((hix - lox) / (hiy - loy));
+    } else {
+      if (v + 1 < r1) edge64[v - r] = make_double4(x[v], y[v], x[v + 1], y[v + 1]);
+    }
+  }
+  for (int32_t f = blockIdx.x * blockDim.x + threadIdx.x; f <= nf; f += stride) {
+    if (kind == GP_PIP) eoff[f] = rvo[fro[f]];
+    else eoff[f] = rvo[f] - f;
+  }
+}
+
+hipError_t launch_build_edges(const int32_t *rvo, const int32_t *fro, const double *x,
+                              const double *y, int32_t nf, int32_t nrings, int32_t nverts,
+                              gp_kind kind, double4 *edge64, float *k32, int32_t *eoff,
+                              hipStream_t s) {
+  size_t work = (size_t)(nverts > nf + 1 ? nverts : nf + 1);
+  hipLaunchKernelGGL(k_build_edges, dim3(grid_for(work, 256, 8192)), dim3(256), 0, s, rvo, fro,
+                     x, y, nf, nrings, nverts, (int)kind, edge64, k32, eoff);
+  return hipGetLastError();
+}
+
+// Feature MBB over all of its vertices; P2P expands by D; both pad by cs*2^-20.
+__global__ void k_mbb(const int32_t *rvo, const int32_t *fro, const double *x, const double *y,
+                      int32_t nf, int kind, double D, double cs, double *mbb) {
+  const double pad = cs * 0x1p-20;
+  for (int32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < nf;
+       f += gridDim.x * blockDim.x) {
+    int32_t v0 = kind == GP_PIP ? rvo[fro[f]] : rvo[f];
+    int32_t v1 = kind == GP_PIP ? rvo[fro[f + 1]] : rvo[f + 1];
+    double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
+    for (int32_t v = v0; v < v1; ++v) {
+      double a = x[v], b = y[v];
+      if (a < mnx) mnx = a;
+      if (a > mxx) mxx = a;
+      if (b < mny) mny = b;
+      if (b > mxy) mxy = b;
+    }
+    if (kind == GP_P2P) {
+      mnx = mnx - D; mny = mny - D; mxx = mxx + D; mxy = mxy + D;
+    }
+    mbb[4 * (size_t)f + 0] = mnx - pad;
+    mbb[4 * (size_t)f + 1] = mny - pad;
+    mbb[4 * (size_t)f + 2] = mxx + pad;
+    mbb[4 * (size_t)f + 3] = mxy + pad;
+  }
+}
+
+hipError_t launch_mbb(const int32_t *rvo, const int32_t *fro, const double *x, const double *y,
+                      int32_t nf, gp_kind kind, double D, double cs, double *mbb,
+                      hipStream_t s) {
+  if (nf == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mbb, dim3(grid_for(nf, 64, 8192)), dim3(64), 0, s, rvo, fro, x, y, nf,
+                     (int)kind, D, cs, mbb);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(1024) void k_extent(const double *mbb, int32_t nf, double *out) {
+  __shared__ double red[4][1024];
+  double lx = INFINITY, ly = INFINITY, hx = -INFINITY, hy = -INFINITY;
+  for (int32_t f = threadIdx.x; f < nf; f += blockDim.x) {
+    lx = fmin(lx, mbb[4 * (size_t)f + 0]);
+    ly = fmin(ly, mbb[4 * (size_t)f + 1]);
+    hx = fmax(hx, mbb[4 * (size_t)f + 2]);
+    hy = fmax(hy, mbb[4 * (size_t)f + 3]);
+  }
+  red[0][threadIdx.x] = lx; red[1][threadIdx.x] = ly;
+  red[2][threadIdx.x] = hx; red[3][threadIdx.x] = hy;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+      red[1][threadIdx.x] = fmin(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+      red[2][threadIdx.x] = fmax(red[2][threadIdx.x], red[2][threadIdx.x + w]);
+      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+hipError_t launch_extent(const double *mbb, int32_t nf, double *out4, hipStream_t s) {
+  hipLaunchKernelGGL(k_extent, dim3(1), dim3(1024), 0, s, mbb, nf, out4);
+  return hipGetLastError();
+}
+
+// Cell index range [lo, hi] an interval [a, b] touches on one axis, clamped to the grid;
+// false when it misses the grid.
+__device__ __forceinline__ bool axis_range(double a, double b, double o, double cs, int32_t n,
+                                           int32_t *lo, int32_t *hi) {
+  double fa = floor((a - o) / cs);
+  double fb = floor((b - o) / cs);
+  if (fb < 0.0 || fa > (double)(n - 1)) return false;
+  *lo = fa < 0.0 ? 0 : (int32_t)fa;
+  *hi = fb > (double)(n - 1) ? n - 1 : (int32_t)fb;
+  return true;
+}
+
+__global__ void k_raster_count(const double *mbb, int32_t nf, double x0, double y0, double cs,
+                               int32_t nx, int32_t ny, uint32_t *cnt) {
+  for (int32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < nf;
+       f += gridDim.x * blockDim.x) {
+    int32_t ax, bx, ay, by;
+    uint32_t c = 0;
+    if (axis_range(mbb[4 * (size_t)f + 0], mbb[4 * (size_t)f + 2], x0, cs, nx, &ax, &bx) &&
+        axis_range(mbb[4 * (size_t)f + 1], mbb[4 * (size_t)f + 3], y0, cs, ny, &ay, &by))
+      c = (uint32_t)(bx - ax + 1) * (uint32_t)(by - ay + 1);
+    cnt[f] = c;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt[nf] = 0;
+}
+
+hipError_t launch_raster_count(const double *mbb, int32_t nf, double x0, double y0, double cs,
+                               int32_t nx, int32_t ny, uint32_t *cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_raster_count, dim3(grid_for(nf + 1, 256, 8192)), dim3(256), 0, s, mbb,
+                     nf, x0, y0, cs, nx, ny, cnt);
+  return hipGetLastError();
+}
+
+// One wavefront per feature: its cells are written row by row, lanes across a row.
+__global__ __launch_bounds__(64) void k_raster_emit(const double *mbb, int32_t nf, double x0,
+                                                    double y0, double cs, int32_t nx,
+                                                    int32_t ny, const uint32_t *off,
+                                                    uint32_t *pcell, uint32_t *pfid) {
+  for (int32_t f = blockIdx.x; f < nf; f += gridDim.x) {
+    int32_t ax, bx, ay, by;
+    if (!axis_range(mbb[4 * (size_t)f + 0], mbb[4 * (size_t)f + 2], x0, cs, nx, &ax, &bx) ||
+        !axis_range(mbb[4 * (size_t)f + 1], mbb[4 * (size_t)f + 3], y0, cs, ny, &ay, &by))
+      continue;
+    uint32_t o = off[f];
+    int32_t w = bx - ax + 1;
+    for (int32_t iy = ay; iy <= by; ++iy)
+      for (int32_t k = threadIdx.x; k < w; k += 64) {
+        uint32_t pos = o + (uint32_t)(iy - ay) * (uint32_t)w + (uint32_t)k;
+        pcell[pos] = (uint32_t)iy * (uint32_t)nx + (uint32_t)(ax + k);
+        pfid[pos] = (uint32_t)f;
+      }
+  }
+}
+
+hipError_t launch_raster_emit(const double *mbb, int32_t nf, double x0, double y0, double cs,
+                              int32_t nx, int32_t ny, const uint32_t *off, uint32_t *pcell,
+                              uint32_t *pfid, hipStream_t s) {
+  if (nf == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_raster_emit, dim3(nf < 65536 ? nf : 65536), dim3(64), 0, s, mbb, nf, x0,
+                     y0, cs, nx, ny, off, pcell, pfid);
+  return hipGetLastError();
+}
+
+__global__ void k_histogram(const uint32_t *keys, size_t n, uint32_t *cnt) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    atomicAdd(&cnt[keys[i]], 1u);
+}
+
+hipError_t launch_histogram(const uint32_t *keys, size_t n, uint32_t *cnt, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_histogram, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, keys, n, cnt);
+  return hipGetLastError();
+}
+
+__global__ void k_cell_edges(const int32_t *cand_off, const int32_t *cand_id, const int32_t *eoff,
+                             int32_t ncells, int64_t *cell_edges) {
+  for (int32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncells;
+       c += gridDim.x * blockDim.x) {
+    int64_t e = 0;
+    for (int32_t k = cand_off[c]; k < cand_off[c + 1]; ++k) {
+      int32_t f = cand_id[k];
+      e += (int64_t)(eoff[f + 1] - eoff[f]);
+    }
+    cell_edges[c] = e;
+  }
+}
+
+hipError_t launch_cell_edges(const int32_t *cand_off, const int32_t *cand_id,
+                             const int32_t *eoff, int32_t ncells, int64_t *cell_edges,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_edges, dim3(grid_for(ncells, 256, 8192)), dim3(256), 0, s, cand_off,
+                     cand_id, eoff, ncells, cell_edges);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------- point pipeline
+
+// Cell id of each point; ncells (sorts last) when outside the extent or not finite.
+__global__ void k_hash(const double *px, const double *py, int64_t n, double x0, double y0,
+                       double cs, int32_t nx, int32_t ny, uint32_t *key) {
+  const uint32_t ncells = (uint32_t)nx * (uint32_t)ny;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double fx = floor((px[i] - x0) / cs);
+    double fy = floor((py[i] - y0) / cs);
+    bool ok = fx >= 0.0 && fx < (double)nx && fy >= 0.0 && fy < (double)ny;
+    key[i] = ok ? (uint32_t)fy * (uint32_t)nx + (uint32_t)fx : ncells;
+  }
+}
+
+hipError_t launch_hash(const double *px, const double *py, int64_t n, double x0, double y0,
+                       double cs, int32_t nx, int32_t ny, uint32_t *key, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hash, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, px, py, n, x0, y0,
+                     cs, nx, ny, key);
+  return hipGetLastError();
+}
+
+// pt_off[c] = number of sorted keys < c, for c in [0, ncells].
+__global__ void k_offsets(const uint32_t *skey, int64_t n, int32_t ncells, int32_t *pt_off) {
+  for (int32_t c = blockIdx.x * blockDim.x + threadIdx.x; c <= ncells;
+       c += gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+      int64_t mid = (lo + hi) >> 1;
+      if (skey[mid] < (uint32_t)c) lo = mid + 1; else hi = mid;
+    }
+    pt_off[c] = (int32_t)lo;
+  }
+}
+
+hipError_t launch_offsets(const uint32_t *skey, int64_t n, int32_t ncells, int32_t *pt_off,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_offsets, dim3(grid_for((size_t)ncells + 1, 256, 8192)), dim3(256), 0, s,
+                     skey, n, ncells, pt_off);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ double cell_cx(const RefineArgs &a, uint32_t cell) {
+  return a.x0 + ((double)(cell % (uint32_t)a.nx) + 0.5) * a.cs;
+}
+__device__ __forceinline__ double cell_cy(const RefineArgs &a, uint32_t cell) {
+  return a.y0 + ((double)(cell / (uint32_t)a.nx) + 0.5) * a.cs;
+}
+
+// Gather the sorted points (FP32 rebased to the cell centre for the mixed form, FP64 for
+// the FP64 form); points that are unpaired (outside the extent, or in a cell without
+// candidates) get their final (-1, +inf) here.
+__global__ void k_gather(RefineArgs a, int64_t n, int mixed, float *xs32, float *ys32,
+                         double *xs64, double *ys64, uint32_t *n_paired) {
+  for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < n;
+       i0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool in = i < n;
+    uint32_t k = in ? a.skey[i] : 0u;
+    uint32_t j = in ? a.perm[i] : 0u;
+    bool paired = in && k < (uint32_t)a.ncells && a.cand_off[k + 1] > a.cand_off[k];
+    uint64_t m = ballot(paired);
+    if (lane_id() == 0 && m) atomicAdd(n_paired, (uint32_t)__popcll(m));
+    if (!in) continue;
+    if (!paired) {
+      a.out_id[j] = -1;
+      if (a.out_dist) a.out_dist[j] = INFINITY;
+      continue;
+    }
+    double x = a.px[j], y = a.py[j];
+    if (mixed) {
+      xs32[i] = (float)(x - cell_cx(a, k));
+      ys32[i] = (float)(y - cell_cy(a, k));
+    } else {
+      xs64[i] = x;
+      ys64[i] = y;
+    }
+  }
+}
+
+hipError_t launch_gather(const RefineArgs &a, int64_t n, bool mixed, uint32_t *n_paired,
+                         float *xs32, float *ys32, double *xs64, double *ys64, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, a, n,
+                     mixed ? 1 : 0, xs32, ys32, xs64, ys64, n_paired);
+  return hipGetLastError();
+}
+
+__global__ void k_item_count(const int32_t *pt_off, const int32_t *cand_off,
+                             const int64_t *cell_edges, int32_t ncells, int32_t chunk,
+                             uint32_t *cnt, unsigned long long *tests) {
+  // the loop bound is uniform per block so that every lane joins the wave reduction
+  for (int32_t c0 = blockIdx.x * blockDim.x; c0 <= ncells; c0 += gridDim.x * blockDim.x) {
+    const int32_t c = c0 + (int32_t)threadIdx.x;
+    uint32_t q = 0;
+    unsigned long long t = 0;
+    if (c < ncells) {
+      int32_t np = pt_off[c + 1] - pt_off[c];
+      int32_t nc = cand_off[c + 1] - cand_off[c];
+      if (np > 0 && nc > 0) {
+        q = (uint32_t)((np + chunk - 1) / chunk);
+        t = (unsigned long long)np * (unsigned long long)cell_edges[c];
+      }
+    }
+    if (c <= ncells) cnt[c] = q;
+    // wavefront reduction of the test count, one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, GP_WAVE);
+    if (lane_id() == 0 && t) atomicAdd(tests, t);
+  }
+}
+
+__global__ void k_item_emit(const int32_t *pt_off, int32_t ncells, int32_t chunk,
+                            const uint32_t *item_off, Item *items) {
+  for (int32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncells;
+       c += gridDim.x * blockDim.x) {
+    uint32_t o = item_off[c], q = item_off[c + 1] - o;
+    int32_t p0 = pt_off[c], np = pt_off[c + 1] - p0;
+    for (uint32_t k = 0; k < q; ++k) {
+      int32_t lo = p0 + (int32_t)k * chunk;
+      int32_t cnt = np - (int32_t)k * chunk;
+      items[o + k] = Item{c, lo, cnt < chunk ? cnt : chunk, 0};
+    }
+  }
+}
+
+hipError_t launch_items(const int32_t *pt_off, const int32_t *cand_off,
+                        const int64_t *cell_edges, int32_t ncells, int32_t chunk,
+                        uint32_t *item_cnt, uint32_t *scan_tmp, Item *items, uint32_t *counters,
+                        unsigned long long *tests, hipStream_t s) {
+  (void)counters;
+  unsigned g = grid_for((size_t)ncells + 1, 256, 8192);
+  hipLaunchKernelGGL(k_item_count, dim3(g), dim3(256), 0, s, pt_off, cand_off, cell_edges,
+                     ncells, chunk, item_cnt, tests);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_exclusive_scan_u32(item_cnt, item_cnt, (size_t)ncells + 1, scan_tmp, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_item_emit, dim3(g), dim3(256), 0, s, pt_off, ncells, chunk, item_cnt,
+                     items);
+  return hipGetLastError();
+}
+
+__global__ void k_copy_perm(const uint32_t *perm, int64_t n, int32_t *out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (int32_t)perm[i];
+}
+
+hipError_t launch_copy_perm(const uint32_t *perm, int64_t n, int32_t *out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_perm, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, perm, n, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------- FP64 tests
+// The two refinement predicates in plain FP64, in the operation order of the
+// definitions (Sec. III.C crossing, Sec. III.B / Fig. 2 segment distance).
+
+// Crossing of the +x ray from p with edge (lo, hi): half-open in y, strictly right.
+__device__ __forceinline__ bool cross64(double px, double py, double lox, double loy, double w,
+                                        double hiy, double h) {
+  bool st = (loy <= py) & (py < hiy);
+  double lhs = (px - lox) * h;
+  double rhs = w * (py - loy);
+  return st & (lhs < rhs);
+}
+
+// Squared distance from p to segment (a, b): endpoint a when t <= 0, endpoint b when
+// t >= L2, else the perpendicular foot.
+__device__ __forceinline__ double seg_d2_64(double px, double py, double ax, double ay,
+                                            double bx, double by) {
+  double dx = bx - ax, dy = by - ay;
+  double wx = px - ax, wy = py - ay;
+  double L2 = dx * dx + dy * dy;
+  double t = wx * dx + wy * dy;
+  if (t <= 0.0) return wx * wx + wy * wy;
+  if (t >= L2) {
+    double ex = px - bx, ey = py - by;
+    return ex * ex + ey * ey;
+  }
+  double c = wx * dy - wy * dx;
+  return (c * c) / L2;
+}
+
+// ------------------------------------------------------------------------- work queue
+
+__device__ __forceinline__ uint32_t next_item(const RefineArgs &a) {
+  uint32_t it = 0;
+  if (lane_id() == 0) it = atomicAdd(a.item_counter, 1u);
+  return uniform(it);
+}
+
+// Append the flagged lanes' sorted positions to the FP64 recheck queue.
+__device__ __forceinline__ void push_recheck(const RefineArgs &a, bool flag, uint32_t pos) {
+  uint64_t m = ballot(flag);
+  if (!m) return;
+  uint32_t base = 0;
+  if (lane_id() == 0) base = atomicAdd(a.rq_count, (uint32_t)__popcll(m));
+  base = uniform(base);
+  if (flag) a.rq[base + __popcll(m & lanemask_lt())] = pos;
+}
+
+// ------------------------------------------------------------------------- PIP, FP64
+
+struct alignas(16) PipRec64 {
+  double lox, loy, hiy, w, h, pad;
+};
+
+template <int PPL>
+__device__ void pip64_item(const RefineArgs &a, const Item it, PipRec64 *lds) {
+  const uint32_t lane = lane_id();
+  const int EC = a.edge_chunk;
+  double px[PPL], py[PPL];
+  int32_t best[PPL];
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    int idx = (int)lane + GP_WAVE * j;
+    bool v = idx < it.npts;
+    px[j] = v ? a.xs64[it.pt_lo + idx] : 0.0;
+    py[j] = v ? a.ys64[it.pt_lo + idx] : 0.0;
+    best[j] = -1;
+  }
+  const int32_t k0 = a.cand_off[it.cell], k1 = a.cand_off[it.cell + 1];
+  for (int32_t k = k0; k < k1; ++k) {
+    const int32_t f = a.cand_id[k];
+    const int32_t e0 = a.eoff[f], e1 = a.eoff[f + 1];
+    uint32_t odd[PPL];
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) odd[j] = 0;
+    for (int32_t s = e0; s < e1; s += EC) {
+      const int cnt = (e1 - s) < EC ? (e1 - s) : EC;
+      __syncthreads();
+      for (int t = lane; t < cnt; t += GP_WAVE) {
+        double4 r = a.edge64[s + t];
+        PipRec64 q;
+        q.lox = r.x; q.loy = r.y; q.hiy = r.w;
+        q.w = r.z - r.x;
+        q.h = r.w - r.y;
+        q.pad = 0.0;
+        lds[t] = q;
+      }
+      __syncthreads();
+      for (int t = 0; t < cnt; ++t) {
+        const PipRec64 q = lds[t];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) odd[j] ^= (uint32_t)cross64(px[j], py[j], q.lox, q.loy, q.w,
+                                                                q.hiy, q.h);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PPL; ++j)
+      if (best[j] < 0 && odd[j]) best[j] = f;
+  }
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    int idx = (int)lane + GP_WAVE * j;
+    if (idx < it.npts) a.out_id[a.perm[it.pt_lo + idx]] = best[j];
+  }
+}
+
+// ------------------------------------------------------------------------- PIP, mixed
+// FP32 on cell-rebased coordinates.  Each staged edge is classified for the cell:
+//  * "plain": for every point of the cell the FP32 decision provably equals the FP64
+//    one -- the edge lies wholly above or below the cell's y band, or wholly left of
+//    the cell, or spans the band strictly while lying wholly right of the cell.  These
+//    run the 4-instruction test (sub, fma, u32 straddle compare, x compare).
+//  * "guarded": the rest (edges through or near the cell, endpoints inside its band).
+//    Their test also raises a flag when the point is within the edge's error bound G
+//    of the edge, or level with an endpoint in FP32; a flagged (point, polygon) pair
+//    sends the point to the FP64 recheck when that polygon could still decide it.
+// G = 2^-22 * (|k| (3B + 3|lo.y|) + |lo.x| + 3B), B the cell half-width bound: four
+// times the rounding error of the FP32 intercept test against the FP64 predicate.
+
+template <int PPL>
+__device__ void pipmix_item(const RefineArgs &a, const Item it, float4 *ldsA, float4 *ldsB,
+                            float *ldsG) {
+  const uint32_t lane = lane_id();
+  const int EC = a.edge_chunk;
+  const double cx = cell_cx(a, (uint32_t)it.cell), cy = cell_cy(a, (uint32_t)it.cell);
+  const float hb = a.half_box;
+  float px[PPL], py[PPL];
+  int32_t best[PPL];
+  bool rq[PPL];
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    int idx = (int)lane + GP_WAVE * j;
+    bool v = idx < it.npts;
+    px[j] = v ? a.xs32[it.pt_lo + idx] : 0.0f;
+    py[j] = v ? a.ys32[it.pt_lo + idx] : 0.0f;
+    best[j] = -1;
+    rq[j] = false;
+  }
+  const int32_t k0 = a.cand_off[it.cell], k1 = a.cand_off[it.cell + 1];
+  for (int32_t k = k0; k < k1; ++k) {
+    const int32_t f = a.cand_id[k];
+    const int32_t e0 = a.eoff[f], e1 = a.eoff[f + 1];
+    uint64_t par[PPL], flg[PPL];
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) { par[j] = 0; flg[j] = 0; }
+    for (int32_t s = e0; s < e1; s += EC) {
+      const int cnt = (e1 - s) < EC ? (e1 - s) : EC;
+      __syncthreads();
+      uint32_t nA = 0, nB = 0;
+      for (int base = 0; base < cnt; base += GP_WAVE) {
+        const int t = base + (int)lane;
+        const bool act = t < cnt;
+        bool careful = false;
+        float4 recA = make_float4(0.f, 0.f, 0.f, 0.f), recB = recA;
+        float G = 0.f;
+        if (act) {
+          const double4 r = a.edge64[s + t];
+          const float kk = a.k32[s + t];
+          const float lx = (float)(r.x - cx), ly = (float)(r.y - cy);
+          const float hy = (float)(r.w - cy);
+          const bool horiz = r.y == r.w;
+          const float h32 = hy - ly;
+          G = 0x1p-22f * (fabsf(kk) * (3.0f * hb + 3.0f * fabsf(ly)) + fabsf(lx) + 3.0f * hb);
+          const bool yout = (ly > hb) || (hy < -hb);
+          const bool ystrict = (ly < -hb) && (hy > hb + 0x1p-20f * h32);
+          const float ya = fmaxf(ly, -hb), yb = fminf(hy, hb);
+          const float xa = fmaf(ya - ly, kk, lx), xb = fmaf(yb - ly, kk, lx);
+          const bool xleft = fmaxf(xa, xb) < -hb - 2.0f * G;
+          const bool xright = fminf(xa, xb) > hb + 2.0f * G;
+          careful = !(horiz || yout || xleft || (ystrict && xright));
+          recA = horiz ? make_float4(0.f, 3.0e38f, 0.f, 0.f) : make_float4(lx, ly, h32, kk);
+          recB = make_float4(lx, ly, hy, kk);
+        }
+        const uint64_t mB = ballot(act && careful), mA = ballot(act && !careful);
+        if (act && careful) {
+          uint32_t p = nB + __popcll(mB & lanemask_lt());
+          ldsB[p] = recB;
+          ldsG[p] = G;
+        }
+        if (act && !careful) ldsA[nA + __popcll(mA & lanemask_lt())] = recA;
+        nA += __popcll(mA);
+        nB += __popcll(mB);
+      }
+      __syncthreads();
+      for (uint32_t t = 0; t < nA; ++t) {
+        const float4 e = ldsA[t];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+          const float ty = py[j] - e.y;
+          const float xi = fmaf(ty, e.w, e.x);
+          const bool c = (__float_as_uint(ty) < __float_as_uint(e.z)) & (px[j] < xi);
+          par[j] ^= ballot(c);
+        }
+      }
+      for (uint32_t t = 0; t < nB; ++t) {
+        const float4 e = ldsB[t];
+        const float G = ldsG[t];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+          const float ty = py[j] - e.y;
+          const bool st = (ty >= 0.0f) & (py[j] < e.z);
+          const bool eq = (ty == 0.0f) | (py[j] == e.z);
+          const float d = fmaf(ty, e.w, e.x) - px[j];
+          const bool c = st & (d > 0.0f);
+          const bool fl = (eq & !(d < -G)) | (st & !(fabsf(d) > G));
+          par[j] ^= ballot(c);
+          flg[j] |= ballot(fl);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      const bool odd = (par[j] >> lane) & 1ull;
+      const bool fl = (flg[j] >> lane) & 1ull;
+      if (best[j] < 0 && !rq[j]) {
+        if (fl) rq[j] = true;
+        else if (odd) best[j] = f;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    const int idx = (int)lane + GP_WAVE * j;
+    const bool v = idx < it.npts;
+    if (v && !rq[j]) a.out_id[a.perm[it.pt_lo + idx]] = best[j];
+    push_recheck(a, v && rq[j], (uint32_t)(it.pt_lo + idx));
+  }
+}
+
+// ------------------------------------------------------------------------- P2P staging
+// A chunk holds the segments of consecutive candidate polylines (a polyline longer
+// than the chunk continues in the next one).  tab[q] = (fid, end slot | continues<<31).
+
+struct alignas(16) SegRec64 {
+  double ax, ay, bx, by, dx, dy, L2, pad;
+};
+
+// ------------------------------------------------------------------------- P2P, FP64
+
+template <int PPL>
+__device__ void p2p64_item(const RefineArgs &a, const Item it, SegRec64 *lds, int2 *tab) {
+  const uint32_t lane = lane_id();
+  const int EC = a.edge_chunk;
+  double px[PPL], py[PPL], best[PPL];
+  int32_t bid[PPL];
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    int idx = (int)lane + GP_WAVE * j;
+    bool v = idx < it.npts;
+    px[j] = v ? a.xs64[it.pt_lo + idx] : 0.0;
+    py[j] = v ? a.ys64[it.pt_lo + idx] : 0.0;
+    best[j] = a.D2_next;  // accept d2 <= fl(D*D); later only strictly smaller
+    bid[j] = -1;
+  }
+  int32_t k = a.cand_off[it.cell];
+  const int32_t k1 = a.cand_off[it.cell + 1];
+  int32_t soff = 0;
+  while (k < k1) {
+    __syncthreads();
+    int filled = 0, ntab = 0;
+    while (k < k1 && filled < EC) {
+      const int32_t f = a.cand_id[k];
+      const int32_t s0 = a.eoff[f] + soff, s1 = a.eoff[f + 1];
+      const int take = (s1 - s0) < (EC - filled) ? (s1 - s0) : (EC - filled);
+      for (int t = lane; t < take; t += GP_WAVE) {
+        const double4 r = a.edge64[s0 + t];
+        SegRec64 q;
+        q.ax = r.x; q.ay = r.y; q.bx = r.z; q.by = r.w;
+        q.dx = r.z - r.x;
+        q.dy = r.w - r.y;
+        q.L2 = q.dx * q.dx + q.dy * q.dy;
+        q.pad = 0.0;
+        lds[filled + t] = q;
+      }
+      filled += take;
+      const bool cont = s0 + take < s1;
+      if (lane == 0) tab[ntab] = make_int2(f, filled | (cont ? (int)0x80000000 : 0));
+      ++ntab;
+      if (cont) soff += take;
+      else { ++k; soff = 0; }
+    }
+    __syncthreads();
+    int start = 0;
+    for (int q = 0; q < ntab; ++q) {
+      const int2 te = tab[q];
+      const int32_t f = te.x;
+      const int end = te.y & 0x7fffffff;
+      for (int t = start; t < end; ++t) {
+        const SegRec64 r = lds[t];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+          const double wx = px[j] - r.ax, wy = py[j] - r.ay;
+          const double tt = wx * r.dx + wy * r.dy;
+          const double da = wx * wx + wy * wy;
+          const double ex = px[j] - r.bx, ey = py[j] - r.by;
+          const double db = ex * ex + ey * ey;
+          const double c = wx * r.dy - wy * r.dx;
+          const double cc = c * c;
+          const bool ca = tt <= 0.0;
+          const bool cb = !ca & (tt >= r.L2);
+          double d2 = ca ? da : db;
+          const bool cp = !ca & !cb;
+          // The perpendicular case divides only when its quotient could still beat
+          // the current best: cc >= fl(best*L2)*(1+2^-49) implies cc/L2 > best.
+          const double lim = (best[j] * r.L2) * (1.0 + 0x1p-49);
+          d2 = cp ? INFINITY : d2;
+          if (cp && cc < lim) d2 = cc / r.L2;
+          if (d2 < best[j]) { best[j] = d2; bid[j] = f; }
+        }
+      }
+      start = end;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    const int idx = (int)lane + GP_WAVE * j;
+    if (idx < it.npts) {
+      const uint32_t o = a.perm[it.pt_lo + idx];
+      a.out_id[o] = bid[j];
+      a.out_dist[o] = bid[j] >= 0 ? sqrt(best[j]) : INFINITY;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------- P2P, mixed
+// FP32 on cell-rebased coordinates with a branch-free clamped projection.  Per point the
+// wave tracks the best and second-best polyline (distinct ids).  With E the largest
+// distance error bound e_s = 16*2^-24*(B*sqrt2 + M_s) over segments near the cell
+// (M_s: largest rebased |coordinate| of the segment), a point is decided in FP32 only
+// when its winner is inside D - E and beats the runner-up by more than 2E, or when
+// nothing is within D + E; every other point is recomputed in FP64.
+
+template <int PPL>
+__device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsS, float *ldsI,
+                            int2 *tab) {
+  const uint32_t lane = lane_id();
+  const int EC = a.edge_chunk;
+  const double cx = cell_cx(a, (uint32_t)it.cell), cy = cell_cy(a, (uint32_t)it.cell);
+  const float hb = a.half_box;
+  const float T = a.p2p_margin;
+  const float near_lim = (float)a.D + T;
+  float px[PPL], py[PPL], b1[PPL], b2[PPL], pm[PPL];
+  int32_t f1[PPL];
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    int idx = (int)lane + GP_WAVE * j;
+    bool v = idx < it.npts;
+    px[j] = v ? a.xs32[it.pt_lo + idx] : 0.0f;
+    py[j] = v ? a.ys32[it.pt_lo + idx] : 0.0f;
+    b1[j] = INFINITY;
+    b2[j] = INFINITY;
+    pm[j] = INFINITY;
+    f1[j] = -1;
+  }
+  float emax = 0.0f;  // per-lane partial of E over the segments this lane staged
+  int32_t k = a.cand_off[it.cell];
+  const int32_t k1 = a.cand_off[it.cell + 1];
+  int32_t soff = 0;
+  while (k < k1) {
+    __syncthreads();
+    int filled = 0, ntab = 0;
+    while (k < k1 && filled < EC) {
+      const int32_t f = a.cand_id[k];
+      const int32_t s0 = a.eoff[f] + soff, s1 = a.eoff[f + 1];
+      const int take = (s1 - s0) < (EC - filled) ? (s1 - s0) : (EC - filled);
+      for (int t = lane; t < take; t += GP_WAVE) {
+        const double4 r = a.edge64[s0 + t];
+        const double ddx = r.z - r.x, ddy = r.w - r.y;
+        const double L2 = ddx * ddx + ddy * ddy;
+        const float ax = (float)(r.x - cx), ay = (float)(r.y - cy);
+        const float bx = (float)(r.z - cx), by = (float)(r.w - cy);
+        ldsS[filled + t] = make_float4(ax, ay, (float)ddx, (float)ddy);
+        ldsI[filled + t] = L2 > 0.0 ? (float)(1.0 / L2) : 0.0f;
+        const float M = fmaxf(fmaxf(fabsf(ax), fabsf(ay)), fmaxf(fabsf(bx), fabsf(by)));
+        const float es = 16.0f * 0x1p-24f * (hb * 1.4143f + M);
+        const float gx = fmaxf(0.0f, fmaxf(fminf(ax, bx) - hb, -hb - fmaxf(ax, bx)));
+        const float gy = fmaxf(0.0f, fmaxf(fminf(ay, by) - hb, -hb - fmaxf(ay, by)));
+        const bool nearc = (gx <= near_lim && gy <= near_lim &&
+                            sqrtf(gx * gx + gy * gy) <= near_lim) || !(es <= 0.5f * T);
+        if (nearc) emax = fmaxf(emax, es);
+      }
+      filled += take;
+      const bool cont = s0 + take < s1;
+      if (lane == 0) tab[ntab] = make_int2(f, filled | (cont ? (int)0x80000000 : 0));
+      ++ntab;
+      if (cont) soff += take;
+      else { ++k; soff = 0; }
+    }
+    __syncthreads();
+    int start = 0;
+    for (int q = 0; q < ntab; ++q) {
+      const int2 te = tab[q];
+      const int32_t f = te.x;
+      const int end = te.y & 0x7fffffff;
+      for (int t = start; t < end; ++t) {
+        const float4 sg = ldsS[t];
+        const float inv = ldsI[t];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+          const float wx = px[j] - sg.x, wy = py[j] - sg.y;
+          const float dot = fmaf(wx, sg.z, wy * sg.w);
+          const float tt = __builtin_amdgcn_fmed3f(dot * inv, 0.0f, 1.0f);
+          const float qx = fmaf(-tt, sg.z, wx), qy = fmaf(-tt, sg.w, wy);
+          pm[j] = fminf(pm[j], fmaf(qx, qx, qy * qy));
+        }
+      }
+      if (!(te.y & (int)0x80000000)) {
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+          if (pm[j] < b1[j]) { b2[j] = b1[j]; b1[j] = pm[j]; f1[j] = f; }
+          else if (pm[j] < b2[j]) b2[j] = pm[j];
+          pm[j] = INFINITY;
+        }
+      }
+      start = end;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) emax = fmaxf(emax, __shfl_xor(emax, off, GP_WAVE));
+  const double E = (double)emax;
+  const double D = a.D;
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    const int idx = (int)lane + GP_WAVE * j;
+    const bool v = idx < it.npts;
+    const double d1 = (double)sqrtf(b1[j]), d2 = (double)sqrtf(b2[j]);
+    const bool hit = (d1 < D - E) && (d2 - d1 > 2.0 * E);
+    const bool miss = d1 > D + E;
+    const bool flag = !(hit || miss);
+    if (v && !flag) {
+      const uint32_t o = a.perm[it.pt_lo + idx];
+      a.out_id[o] = hit ? f1[j] : -1;
+      a.out_dist[o] = hit ? d1 : INFINITY;
+    }
+    push_recheck(a, v && flag, (uint32_t)(it.pt_lo + idx));
+  }
+}
+
+// ------------------------------------------------------------------------- refine kernels
+
+template <int PPL>
+__global__ __launch_bounds__(64) void k_pip64(RefineArgs a, int persistent) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  PipRec64 *lds = (PipRec64 *)smem;
+  const uint32_t n_items = *a.n_items;
+  uint32_t it = persistent ? next_item(a) : blockIdx.x;
+  while (it < n_items) {
+    pip64_item<PPL>(a, a.items[it], lds);
+    if (!persistent) break;
+    it = next_item(a);
+  }
+}
+
+template <int PPL>
+__global__ __launch_bounds__(64) void k_pipmix(RefineArgs a, int persistent) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  float4 *A = (float4 *)smem;
+  float4 *B = A + a.edge_chunk;
+  float *G = (float *)(B + a.edge_chunk);
+  const uint32_t n_items = *a.n_items;
+  uint32_t it = persistent ? next_item(a) : blockIdx.x;
+  while (it < n_items) {
+    pipmix_item<PPL>(a, a.items[it], A, B, G);
+    if (!persistent) break;
+    it = next_item(a);
+  }
+}
+
+template <int PPL>
+__global__ __launch_bounds__(64) void k_p2p64(RefineArgs a, int persistent) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  SegRec64 *lds = (SegRec64 *)smem;
+  int2 *tab = (int2 *)(lds + a.edge_chunk);
+  const uint32_t n_items = *a.n_items;
+  uint32_t it = persistent ? next_item(a) : blockIdx.x;
+  while (it < n_items) {
+    p2p64_item<PPL>(a, a.items[it], lds, tab);
+    if (!persistent) break;
+    it = next_item(a);
+  }
+}
+
+template <int PPL>
+__global__ __launch_bounds__(64) void k_p2pmix(RefineArgs a, int persistent) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  float4 *S = (float4 *)smem;
+  float *I = (float *)(S + a.edge_chunk);
+  int2 *tab = (int2 *)(I + a.edge_chunk);
+  const uint32_t n_items = *a.n_items;
+  uint32_t it = persistent ? next_item(a) : blockIdx.x;
+  while (it < n_items) {
+    p2pmix_item<PPL>(a, a.items[it], S, I, tab);
+    if (!persistent) break;
+    it = next_item(a);
+  }
+}
+
+static size_t refine_lds_bytes(gp_kind kind, gp_precision prec, int ec) {
+  if (kind == GP_PIP)
+    return prec == GP_FP64 ? (size_t)ec * sizeof(PipRec64) : (size_t)ec * (16 + 16 + 4);
+  return prec == GP_FP64 ? (size_t)ec * (sizeof(SegRec64) + sizeof(int2))
+                         : (size_t)ec * (16 + 4 + sizeof(int2));
+}
+
+#define GP_DISPATCH(KERNEL, PPLV, ...)                                             \
+  do {                                                                             \
+    if ((PPLV) == 1) hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__);                   \
+    else if ((PPLV) == 2) hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__);              \
+    else hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__);                               \
+  } while (0)
+
+hipError_t launch_refine(gp_kind kind, gp_precision prec, const RefineArgs &a,
+                         const gp_tuning &t, int num_cu, int64_t max_items, hipStream_t s) {
+  const int ppl = t.points_per_lane;
+  const size_t lds = refine_lds_bytes(kind, prec, a.edge_chunk);
+  unsigned grid;
+  if (t.persistent) {
+    int64_t g = (int64_t)num_cu * t.wg_per_cu;
+    if (g > max_items) g = max_items;
+    grid = (unsigned)(g < 1 ? 1 : g);
+  } else {
+    grid = (unsigned)(max_items < 1 ? 1 : max_items);
+  }
+  const int pers = t.persistent ? 1 : 0;
+  if (kind == GP_PIP && prec == GP_FP64)
+    GP_DISPATCH(k_pip64, ppl, dim3(grid), dim3(64), lds, s, a, pers);
+  else if (kind == GP_PIP)
+    GP_DISPATCH(k_pipmix, ppl, dim3(grid), dim3(64), lds, s, a, pers);
+  else if (prec == GP_FP64)
+    GP_DISPATCH(k_p2p64, ppl, dim3(grid), dim3(64), lds, s, a, pers);
+  else
+    GP_DISPATCH(k_p2pmix, ppl, dim3(grid), dim3(64), lds, s, a, pers);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------- FP64 recheck
+// One thread per queued point: the point's full result over all candidates of its cell,
+// in FP64 with the definitions' operation order, straight from the edge records.
+
+__global__ void k_recheck_pip(RefineArgs a) {
+  const uint32_t nq = *a.rq_count;
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+    const uint32_t i = a.rq[q];
+    const uint32_t j = a.perm[i], cell = a.skey[i];
+    const double x = a.px[j], y = a.py[j];
+    int32_t best = -1;
+    for (int32_t k = a.cand_off[cell]; k < a.cand_off[cell + 1] && best < 0; ++k) {
+      const int32_t f = a.cand_id[k];
+      uint32_t odd = 0;
+      for (int32_t e = a.eoff[f]; e < a.eoff[f + 1]; ++e) {
+        const double4 r = a.edge64[e];
+        odd ^= (uint32_t)cross64(x, y, r.x, r.y, r.z - r.x, r.w, r.w - r.y);
+      }
+      if (odd) best = f;
+    }
+    a.out_id[j] = best;
+  }
+}
+
+__global__ void k_recheck_p2p(RefineArgs a) {
+  const uint32_t nq = *a.rq_count;
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+    const uint32_t i = a.rq[q];
+    const uint32_t j = a.perm[i], cell = a.skey[i];
+    const double x = a.px[j], y = a.py[j];
+    int32_t bid = -1;
+    double best = INFINITY;
+    for (int32_t k = a.cand_off[cell]; k < a.cand_off[cell + 1]; ++k) {
+      const int32_t f = a.cand_id[k];
+      double pd = INFINITY;
+      for (int32_t e = a.eoff[f]; e < a.eoff[f + 1]; ++e) {
+        const double4 r = a.edge64[e];
+        const double d2 = seg_d2_64(x, y, r.x, r.y, r.z, r.w);
+        if (d2 < pd) pd = d2;
+      }
+      if (pd <= a.D2 && pd < best) { best = pd; bid = f; }
+    }
+    a.out_id[j] = bid;
+    a.out_dist[j] = bid >= 0 ? sqrt(best) : INFINITY;
+  }
+}
+
+hipError_t launch_recheck(gp_kind kind, const RefineArgs &a, int num_cu, hipStream_t s) {
+  dim3 grid((unsigned)(num_cu > 0 ? num_cu * 2 : 512)), block(64);
+  if (kind == GP_PIP) hipLaunchKernelGGL(k_recheck_pip, grid, block, 0, s, a);
+  else hipLaunchKernelGGL(k_recheck_p2p, grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace gp

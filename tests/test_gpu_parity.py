@@ -1,0 +1,416 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI.
+
+Bars: grid pairing, PIP ids and P2P ids bit-exact; P2P distances bitwise for the FP64
+form and within 1e-3 (absolute, input units) for the mixed form.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1403_0802_amd import synth
+from tests import pins
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MIXED_TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def gp():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_1403_0802_amd import gp as gpmod
+    return gpmod
+
+
+def dev_arrays(*arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda() for a in arrs]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def run_gpu(gp, grid, px, py, prec, stats=False, tuning=None):
+    if tuning is not None:
+        gp.gp_set_tuning(grid, prec, **tuning)
+    tx, ty = dev_arrays(px, py)
+    r = gp.run(grid, tx, ty, prec, stats=stats)
+    torch.cuda.synchronize()
+    if grid.kind == gp.GP_PIP:
+        if stats:
+            return r[0].cpu().numpy(), r[1]
+        return r.cpu().numpy()
+    if stats:
+        return r[0].cpu().numpy(), r[1].cpu().numpy(), r[2]
+    return r[0].cpu().numpy(), r[1].cpu().numpy()
+
+
+def check_p2p(got_id, got_d, want_id, want_d, prec, where=""):
+    assert np.array_equal(got_id, want_id), f"{where}: {np.sum(got_id != want_id)} ids differ"
+    hit = want_id >= 0
+    assert np.all(np.isinf(got_d[~hit])), where
+    if prec == "fp64":
+        assert np.array_equal(got_d, want_d), f"{where}: FP64 distances are not bitwise equal"
+    else:
+        err = np.abs(got_d[hit] - want_d[hit])
+        assert err.size == 0 or err.max() <= MIXED_TOL, f"{where}: max err {err.max()}"
+        return float(err.max()) if err.size else 0.0
+    return 0.0
+
+
+# ---------------------------------------------------------------------------- pairing
+
+
+@pytest.mark.parametrize("case", ["c1", "c2", "c2_derived", "on_lines"])
+def test_pairing_bit_exact(gp, case):
+    say("pairing", case)
+    if case == "c1":
+        w = synth.config1()
+    elif case == "on_lines":
+        g = pins.polygons([[pins.box(0.25, 0.5, 0.75, 0.625)], [pins.box(0.125, 0.0, 0.5, 0.25)]])
+        rng = np.random.default_rng(3)
+        w = synth.Workload("on_lines", "pip", g, rng.uniform(-0.1, 1.1, 50_000),
+                           rng.uniform(-0.1, 1.1, 50_000),
+                           synth.GridParams(cell_size=1.0 / 64, nx=64, ny=64), {})
+    else:
+        w = synth.config2(n_points=300_000, n_lines=5_000)
+        if case == "c2_derived":
+            w.params = synth.GridParams(cell_size=100.0, radius_D=50.0)
+    og = oracle.build_grid(w.geom, w.params)
+    grid = gp.gp_build_grid(w.kind, w.geom, w.params)
+    info = grid.info()
+    assert (info["x0"], info["y0"], info["nx"], info["ny"]) == (og.x0, og.y0, og.nx, og.ny)
+    off, ids = grid.candidates()
+    assert np.array_equal(off.astype(np.int64), og.cand_off)
+    assert np.array_equal(ids, og.cand_id)
+    # point side
+    tx, ty = dev_arrays(w.px, w.py)
+    n = len(w.px)
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    pt_off = torch.empty(og.ncells + 1, dtype=torch.int32, device="cuda")
+    ws = gp.new_workspace(grid, n, "fp64")
+    gp.gp_pair_points(grid, tx, ty, perm, pt_off, ws)
+    torch.cuda.synchronize()
+    cells = oracle.point_cells(og, w.px, w.py)
+    want_off, want_perm = oracle.sort_points(og, cells)
+    assert np.array_equal(perm.cpu().numpy().astype(np.int64), want_perm)
+    assert np.array_equal(pt_off.cpu().numpy().astype(np.int64), want_off)
+    # test count
+    r = run_gpu(gp, grid, w.px, w.py, "fp64", stats=True)
+    st = r[-1]
+    assert st["tests"] == oracle.test_count(og, w.px, w.py)
+    assert st["n_paired"] == int(sum(np.diff(og.cand_off)[cells[cells >= 0]] > 0))
+
+
+# ---------------------------------------------------------------------------- C1 / C2
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = synth.config1()
+    g, want = oracle.run(w)
+    return w, want
+
+
+@pytest.fixture(scope="module")
+def c2():
+    w = synth.config2()
+    g, want_id, want_d = oracle.run(w)
+    return w, want_id, want_d
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_pip_c1(gp, c1, prec):
+    w, want = c1
+    say("pip c1", prec)
+    grid = gp.gp_build_grid("pip", w.geom, w.params)
+    got, st = run_gpu(gp, grid, w.px, w.py, prec, stats=True)
+    assert np.array_equal(got, want), f"{np.sum(got != want)} ids differ"
+    say("  stats", st)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_p2p_c2(gp, c2, prec):
+    w, want_id, want_d = c2
+    say("p2p c2", prec)
+    grid = gp.gp_build_grid("p2p", w.geom, w.params)
+    gid, gd, st = run_gpu(gp, grid, w.px, w.py, prec, stats=True)
+    err = check_p2p(gid, gd, want_id, want_d, prec, "c2")
+    say("  stats", st, "max abs distance error", err)
+
+
+# ---------------------------------------------------------------------------- tuning
+
+
+TUNINGS = [dict(points_per_lane=p, edge_chunk=e, wg_per_cu=wg, persistent=pe)
+           for p in (1, 2, 4) for e in (64, 256, 512) for wg, pe in ((8, 1), (2, 1), (8, 0))]
+
+
+@pytest.mark.parametrize("kind", ["pip", "p2p"])
+def test_results_invariant_under_tuning(gp, kind):
+    """Every kernel configuration gives the same bits; so does a second run."""
+    say("tuning sweep", kind)
+    if kind == "pip":
+        w = synth.config1(n_points=60_000, grid_n=6, seed_salt=3)
+        _, want = oracle.run(w)
+    else:
+        w = synth.config2(n_points=200_000, n_lines=4_000, seed_salt=3)
+        _, want_id, want_d = oracle.run(w)
+    grid = gp.gp_build_grid(kind, w.geom, w.params)
+    for prec in ("fp64", "mixed"):
+        ref = None
+        for t in TUNINGS:
+            r = run_gpu(gp, grid, w.px, w.py, prec, tuning=t)
+            if kind == "pip":
+                assert np.array_equal(r, want), (prec, t)
+            else:
+                check_p2p(r[0], r[1], want_id, want_d, prec, f"{prec} {t}")
+            if ref is None:
+                ref = r
+            elif kind == "pip":
+                assert np.array_equal(r, ref)
+            else:
+                assert np.array_equal(r[0], ref[0]) and np.array_equal(r[1], ref[1]), (prec, t)
+
+
+def test_shuffle_invariance(gp):
+    say("shuffle")
+    w = synth.config2(n_points=100_000, n_lines=3_000, seed_salt=4)
+    grid = gp.gp_build_grid("p2p", w.geom, w.params)
+    perm = np.random.default_rng(0).permutation(len(w.px))
+    for prec in ("fp64", "mixed"):
+        a_id, a_d = run_gpu(gp, grid, w.px, w.py, prec)
+        b_id, b_d = run_gpu(gp, grid, w.px[perm], w.py[perm], prec)
+        assert np.array_equal(a_id[perm], b_id) and np.array_equal(a_d[perm], b_d)
+
+
+# ---------------------------------------------------------------------------- edge cases
+
+
+def test_empty_and_unpaired_inputs(gp):
+    say("empty / unpaired")
+    w = synth.config1(n_points=10, grid_n=4)
+    grid = gp.gp_build_grid("pip", w.geom, w.params)
+    ws = gp.new_workspace(grid, 0, "mixed")
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    out = torch.empty(0, dtype=torch.int32, device="cuda")
+    st = gp.gp_pip(grid, e, e, out, "mixed", ws, stats=True)
+    assert st["n_points"] == 0
+    px = np.array([-0.5, 1.0, 2.0, np.nan, np.inf, -np.inf, 0.5, np.nan])
+    py = np.array([0.5, 0.5, 0.5, 0.5, 0.5, 0.5, np.nan, np.nan])
+    for prec in ("fp64", "mixed"):
+        assert np.all(run_gpu(gp, grid, px, py, prec) == -1)
+    w2 = synth.config2(n_points=10, n_lines=50)
+    g2 = gp.gp_build_grid("p2p", w2.geom, w2.params)
+    for prec in ("fp64", "mixed"):
+        gid, gd = run_gpu(gp, g2, px * 1e5, py * 1e5, prec)
+        assert np.all(gid == -1) and np.all(np.isinf(gd))
+
+
+def test_points_on_vertices_edges_and_vertex_heights(gp):
+    """Points exactly on polygon vertices, on edge midpoints, and level with vertices,
+    plus their nearest representable neighbours."""
+    say("on-boundary PIP")
+    w = synth.config1(n_points=10, grid_n=5, seed_salt=9)
+    g = w.geom
+    rng = np.random.default_rng(1)
+    x, y = g.x, g.y
+    nxt = np.arange(len(x)) + 1
+    rvo = g.ring_vert_off
+    for r in range(len(rvo) - 1):
+        nxt[rvo[r + 1] - 1] = rvo[r]
+    mx, my = 0.5 * (x + x[nxt]), 0.5 * (y + y[nxt])
+    lvl_x = rng.uniform(0, 1, len(y))
+    px = np.concatenate([x, mx, lvl_x, np.nextafter(x, 2), np.nextafter(mx, -1), x])
+    py = np.concatenate([y, my, y, y, my, np.nextafter(y, 2)])
+    want = oracle.pip(g, px, py, oracle.build_grid(g, w.params))
+    grid = gp.gp_build_grid("pip", g, w.params)
+    for prec in ("fp64", "mixed"):
+        got = run_gpu(gp, grid, px, py, prec)
+        assert np.array_equal(got, want), (prec, np.sum(got != want))
+
+
+def test_holes_overlaps_and_long_rings(gp):
+    """Nested holes, overlapping polygons (smallest id wins), a 5,000-vertex ring that
+    spans several LDS chunks, a ring with a repeated closing vertex and a nearly
+    horizontal edge."""
+    say("holes / overlaps / long rings")
+    rng = np.random.default_rng(5)
+    t = np.sort(rng.uniform(0, 2 * np.pi, 5000))
+    big = list(zip(0.5 + 0.45 * np.cos(t), 0.5 + 0.45 * np.sin(t)))
+    sq = pins.box(0.2, 0.2, 0.8, 0.8)
+    hole = pins.box(0.3, 0.3, 0.7, 0.7, ccw=False)
+    dup = pins.box(0.1, 0.6, 0.4, 0.9) + [(0.1, 0.6)]
+    flat = [(0.05, 0.05), (0.95, 0.05 + 1e-13), (0.95, 0.2), (0.05, 0.2)]
+    g = pins.polygons([[sq, hole], [big], [dup], [flat]])
+    params = synth.GridParams(cell_size=1 / 32, nx=32, ny=32)
+    px, py = rng.uniform(0, 1, (2, 200_000))
+    px = np.concatenate([px, rng.uniform(0.05, 0.95, 20_000)])
+    py = np.concatenate([py, 0.05 + 1e-13 * rng.uniform(-1, 2, 20_000)])
+    want = oracle.pip(g, px, py, oracle.build_grid(g, params))
+    assert np.array_equal(want, oracle.pip(g, px, py))
+    grid = gp.gp_build_grid("pip", g, params)
+    for prec in ("fp64", "mixed"):
+        got = run_gpu(gp, grid, px, py, prec)
+        assert np.array_equal(got, want), (prec, np.sum(got != want))
+
+
+def test_near_edge_sweep_mixed(gp):
+    """Points at distances 1e-15 .. 1e-3 (relative to the unit square) from polygon
+    edges, on both sides: the guard band must send every doubtful one to FP64."""
+    say("near-edge sweep")
+    geom, _ = synth.config3_geometry(n_polygons=200, median_v=100, max_v=2000, seed_salt=2)
+    rng = np.random.default_rng(8)
+    x, y = geom.x, geom.y
+    nxt = np.arange(len(x)) + 1
+    rvo = geom.ring_vert_off
+    for r in range(len(rvo) - 1):
+        nxt[rvo[r + 1] - 1] = rvo[r]
+    k = rng.integers(0, len(x), 300_000)
+    s = rng.uniform(0, 1, len(k))
+    ex, ey = x[nxt[k]] - x[k], y[nxt[k]] - y[k]
+    L = np.hypot(ex, ey) + 1e-300
+    nrm_x, nrm_y = -ey / L, ex / L
+    dist = 10.0 ** rng.uniform(-15, -3, len(k)) * rng.choice([-1, 1], len(k))
+    px = x[k] + s * ex + dist * nrm_x
+    py = y[k] + s * ey + dist * nrm_y
+    ok = (px >= 0) & (px < 1) & (py >= 0) & (py < 1)
+    px, py = px[ok], py[ok]
+    params = synth.GridParams(cell_size=1 / 256, nx=256, ny=256)
+    want = oracle.pip(geom, px, py, oracle.build_grid(geom, params))
+    grid = gp.gp_build_grid("pip", geom, params)
+    got64 = run_gpu(gp, grid, px, py, "fp64")
+    assert np.array_equal(got64, want)
+    got, st = run_gpu(gp, grid, px, py, "mixed", stats=True)
+    assert np.array_equal(got, want), np.sum(got != want)
+    say("  rechecked", st["n_rechecked"], "of", len(px))
+
+
+def test_p2p_ties_range_and_degenerate_segments(gp):
+    say("p2p ties / range / degenerate")
+    lines = [[(0.0, 2.0), (10.0, 2.0)], [(0.0, -2.0), (10.0, -2.0)], [(0.0, 5.0), (10.0, 5.0)],
+             [(3.0, 3.0), (3.0, 3.0), (4.0, 3.5)],  # zero-length first segment
+             [(20.0, 20.0)] * 3]  # all-degenerate polyline
+    # one polyline with 1500 segments, longer than any LDS chunk
+    t = np.linspace(0, 1, 1501)
+    lines.append(list(zip(30 + 10 * np.cos(6 * t), 30 + 10 * np.sin(6 * t))))
+    g = pins.polylines(lines)
+    params = synth.GridParams(cell_size=1.0, radius_D=2.0, x0=-10, y0=-10, nx=64, ny=64)
+    rng = np.random.default_rng(2)
+    px = np.concatenate([[5.0, 5.0, 5.0, 5.0, 20.0, 20.0 + 2.0, 3.0],
+                         rng.uniform(-8, 50, 100_000)])
+    py = np.concatenate([[0.0, 3.0, 7.0, np.nextafter(-4.0, -5.0), 20.0, 20.0, 1.0],
+                         rng.uniform(-8, 50, 100_000)])
+    og = oracle.build_grid(g, params)
+    want_id, want_d = oracle.p2p(g, px, py, params.radius_D, og)
+    assert want_id[:5].tolist() == [0, 0, 2, -1, 4]
+    grid = gp.gp_build_grid("p2p", g, params)
+    for prec in ("fp64", "mixed"):
+        gid, gd = run_gpu(gp, grid, px, py, prec)
+        check_p2p(gid, gd, want_id, want_d, prec, prec)
+
+
+def test_p2p_near_range_and_near_tie_sweep(gp):
+    """Points at D +- 1e-9..1e-3 from segments and almost equidistant between two
+    polylines: the mixed form must recheck whatever it cannot decide."""
+    say("p2p near-D / near-tie sweep")
+    w = synth.config2(n_points=10, n_lines=3_000, seed_salt=6)
+    g = w.geom
+    D = w.params.radius_D
+    rng = np.random.default_rng(4)
+    x, y = g.x, g.y
+    rvo = g.ring_vert_off
+    seg = np.concatenate([np.arange(rvo[f], rvo[f + 1] - 1) for f in range(g.n_features)])
+    k = rng.choice(seg, 200_000)
+    s = rng.uniform(0, 1, len(k))
+    ex, ey = x[k + 1] - x[k], y[k + 1] - y[k]
+    L = np.hypot(ex, ey) + 1e-300
+    off = D + 10.0 ** rng.uniform(-9, -3, len(k)) * rng.choice([-1, 1], len(k))
+    px = x[k] + s * ex - ey / L * off
+    py = y[k] + s * ey + ex / L * off
+    # midpoints between vertices of different polylines
+    a, b = rng.integers(0, len(x), (2, 100_000))
+    px = np.concatenate([px, 0.5 * (x[a] + x[b])])
+    py = np.concatenate([py, 0.5 * (y[a] + y[b])])
+    ok = (px >= 0) & (px < 40_000) & (py >= 0) & (py < 40_000)
+    px, py = px[ok], py[ok]
+    og = oracle.build_grid(g, w.params)
+    want_id, want_d = oracle.p2p(g, px, py, D, og)
+    grid = gp.gp_build_grid("p2p", g, w.params)
+    for prec in ("fp64", "mixed"):
+        gid, gd, st = run_gpu(gp, grid, px, py, prec, stats=True)
+        err = check_p2p(gid, gd, want_id, want_d, prec, prec)
+        say("  ", prec, "rechecked", st["n_rechecked"], "max err", err)
+
+
+def test_derived_extent_and_single_cell(gp):
+    say("derived extent / single cell")
+    w = synth.config1(n_points=30_000, grid_n=3, seed_salt=7)
+    for params in (synth.GridParams(cell_size=1 / 50), synth.GridParams(cell_size=10.0)):
+        og = oracle.build_grid(w.geom, params)
+        want = oracle.pip(w.geom, w.px, w.py, og)
+        grid = gp.gp_build_grid("pip", w.geom, params)
+        for prec in ("fp64", "mixed"):
+            assert np.array_equal(run_gpu(gp, grid, w.px, w.py, prec), want)
+
+
+def test_bad_geometry_is_rejected(gp):
+    g = pins.polylines([[(0.0, 0.0), (1.0, 1.0)], [(2.0, 2.0)]])
+    with pytest.raises(gp.GPError) as e:
+        gp.gp_build_grid("p2p", g, synth.GridParams(cell_size=1.0, radius_D=1.0))
+    assert e.value.status == gp.GP_E_BAD_GEOMETRY
+    g = pins.polygons([[pins.box(0.0, 0.0, 1.0, 1.0)]])
+    g.x[1] = np.nan
+    with pytest.raises(gp.GPError) as e:
+        gp.gp_build_grid("pip", g, synth.GridParams(cell_size=0.5))
+    assert e.value.status == gp.GP_E_BAD_GEOMETRY
+
+
+# ---------------------------------------------------------------------------- scale
+
+
+@pytest.fixture(scope="module")
+def c3_geom():
+    return synth.config3_geometry()
+
+
+def test_c3_mixed_equals_fp64_and_oracle_sample(gp, c3_geom):
+    """Configuration 3 geometry (5,000 polygons, up to 50,000 vertices, holes) with 4M
+    points: mixed ids == FP64 ids bitwise; a sample of 20,000 == the oracle."""
+    geom, _ = c3_geom
+    say("c3 4M points")
+    px, py = synth.config3_points(4_000_000)
+    params = synth.GridParams(cell_size=1 / 1024, nx=1024, ny=1024)
+    grid = gp.gp_build_grid("pip", geom, params)
+    g64, s64 = run_gpu(gp, grid, px, py, "fp64", stats=True)
+    gmx, smx = run_gpu(gp, grid, px, py, "mixed", stats=True)
+    assert np.array_equal(g64, gmx), np.sum(g64 != gmx)
+    idx = np.random.default_rng(0).choice(len(px), 20_000, replace=False)
+    og = oracle.build_grid(geom, params)
+    want = oracle.pip(geom, px[idx], py[idx], og)
+    assert np.array_equal(g64[idx], want)
+    assert smx["tests"] == s64["tests"]
+    say("  fp64", s64, "\n  mixed", smx)
+
+
+def test_c4_scaled_mixed_vs_oracle_sample(gp):
+    say("c4 geometry, 8M points")
+    geom = synth.config4_geometry()
+    px, py = synth.config4_points(8_000_000)
+    params = synth.GridParams(cell_size=100.0, radius_D=100.0, nx=400, ny=400)
+    grid = gp.gp_build_grid("p2p", geom, params)
+    i64, d64, s64 = run_gpu(gp, grid, px, py, "fp64", stats=True)
+    imx, dmx, smx = run_gpu(gp, grid, px, py, "mixed", stats=True)
+    assert np.array_equal(i64, imx), np.sum(i64 != imx)
+    hit = i64 >= 0
+    err = np.abs(d64[hit] - dmx[hit])
+    assert err.max() <= MIXED_TOL
+    idx = np.random.default_rng(1).choice(len(px), 20_000, replace=False)
+    og = oracle.build_grid(geom, params)
+    wid, wd = oracle.p2p(geom, px[idx], py[idx], 100.0, og)
+    check_p2p(i64[idx], d64[idx], wid, wd, "fp64", "c4 sample")
+    say("  fp64", s64, "\n  mixed", smx, "\n  max err", err.max())
