@@ -1,0 +1,320 @@
+"""Benchmark: point-edge tests per second of the grid-filtered PIP + P2P refinement.
+
+One step is one query batch through the whole per-batch path (cell hash, stable sort,
+gather/rebase, work items, refinement, FP64 recheck, output) for BOTH operations:
+  PIP  configuration 3: 50M points against 5,000 Voronoi polygons (holes, up to
+       50,000 vertices), grid 1024 x 1024;
+  P2P  configuration 4: 200M points against 200,000 random-walk polylines, D = 100 m,
+       grid 400 x 400 of 100 m cells;
+in the mixed-precision form.  The grids (MBBs, rasterised candidate lists) are built
+once per geometry set and stay resident, as in a serving deployment; their build time
+is reported separately.  Inputs are resident in HBM before the timed region starts.
+
+Printed: ONE JSON line (rank 0).  Multi-GPU runs are not supported by this build.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "point-edge tests/sec (PIP, P2P) vs FP32-ALU roofline; serving p50/p99 latency"
+FP32_PEAK = 157.3e12  # MI355X vector FP32, TFLOP/s (published)
+FP64_PEAK = 78.6e12   # MI355X vector FP64
+F_PIP = 6             # algorithmic FLOP per PIP point-edge test
+F_P2P = 14            # algorithmic FLOP per P2P point-segment test
+KERNEL_SRC = os.path.join(ROOT, "paper_1403_0802_amd", "csrc", "gp_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE runs, if they were taken
+    on the current kernel source (else None)."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    e = t.get(kernel)
+    if not e or e.get("kernel_source_sha") != kernel_hash() or e.get("workload") != workload:
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def build_workloads(scale: float):
+    from paper_1403_0802_amd import synth
+    t0 = time.time()
+    geom3, info3 = synth.config3_geometry()
+    p3 = synth.GridParams(cell_size=1 / 1024, nx=1024, ny=1024)
+    n3 = int(50_000_000 * scale)
+    px3, py3 = synth.config3_points(n3)
+    geom4 = synth.config4_geometry()
+    p4 = synth.GridParams(cell_size=100.0, radius_D=100.0, nx=400, ny=400)
+    n4 = int(200_000_000 * scale)
+    px4, py4 = synth.config4_points(n4)
+    log(f"[bench] inputs generated in {time.time() - t0:.1f}s: C3 {n3} pts / "
+        f"{geom3.n_vertices} verts, C4 {n4} pts / {geom4.n_vertices} verts")
+    return (geom3, p3, px3, py3), (geom4, p4, px4, py4)
+
+
+def cpu_baseline(c3, c4, budget_s: float):
+    """The CPU oracle as it stands (grid-filtered, FP64, OpenMP over points) on all host
+    threads, on bounded samples of the same workloads."""
+    import oracle
+    lib = oracle.load()
+    threads = len(os.sched_getaffinity(0))
+    geom3, p3, px3, py3 = c3
+    geom4, p4, px4, py4 = c4
+    g3 = oracle.build_grid(geom3, p3, lib)
+    g4 = oracle.build_grid(geom4, p4, lib)
+    out = {}
+    tests_total = 0
+    secs_total = 0.0
+    for name, geom, g, px, py, start in (("pip", geom3, g3, px3, py3, 20_000),
+                                         ("p2p", geom4, g4, px4, py4, 200_000)):
+        m = start
+        while True:
+            sx, sy = px[:m], py[:m]
+            t0 = time.perf_counter()
+            if name == "pip":
+                oracle.pip(geom, sx, sy, g, threads, lib)
+            else:
+                oracle.p2p(geom, sx, sy, p4.radius_D, g, threads, lib)
+            dt = time.perf_counter() - t0
+            if dt > budget_s / 4 or m >= len(px):
+                break
+            m = min(len(px), int(m * max(2.0, budget_s / 2 / max(dt, 1e-3))))
+        tests = oracle.test_count(g, px[:m], py[:m], lib)
+        out[name] = {"points": m, "tests": tests, "seconds": dt, "tests_per_s": tests / dt}
+        tests_total += tests
+        secs_total += dt
+    return {
+        "value": tests_total / secs_total,
+        "unit": "tests/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"first {out['pip']['points']} C3 points (PIP) and first "
+                   f"{out['p2p']['points']} C4 points (P2P), FP64 oracle with its own grid, "
+                   f"OpenMP over points"),
+        "pip_tests_per_s": out["pip"]["tests_per_s"],
+        "p2p_tests_per_s": out["p2p"]["tests_per_s"],
+    }
+
+
+def serving_run(gp, torch, grid3, grid4, n_requests: int, precision: str):
+    """Configuration 5: a Poisson stream of mixed PIP/P2P batches (log-uniform 1K-4M
+    points) against the resident grids, offered at ~70% of the rate sustained during
+    warm-up; latency is submit -> results visible, measured inside the server."""
+    from paper_1403_0802_amd import synth
+    dev = torch.device("cuda")
+    reqs = synth.serving_stream(n_requests, rate_per_s=1.0)
+    data, outs = [], []
+    for (_, kind, n, i) in reqs:
+        x, y = synth.request_points(kind, n, i)
+        data.append((kind, torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)))
+        oid = torch.empty(n, dtype=torch.int32, device=dev)
+        od = torch.empty(n, dtype=torch.float64, device=dev) if kind == "p2p" else None
+        outs.append((oid, od))
+    slots, slot_points = 4, 1 << 22
+    srv = gp.Server(grid3, grid4, n_slots=slots, slot_points=slot_points, mem_budget=24 << 30,
+                    precision=precision, inputs_on_device=True, use_graphs=True)
+    # warm-up: every request once, back to back (captures the graphs); sustained rate
+    t0 = time.perf_counter()
+    for t in [srv.submit(k, x, y, o[0], o[1]) for (k, x, y), o in zip(data, outs)]:
+        srv.wait(t)
+    rate_pts = sum(x.numel() for _, x, _ in data) / (time.perf_counter() - t0)
+    mean_pts = float(np.mean([x.numel() for _, x, _ in data]))
+    lam = 0.7 * rate_pts / mean_pts
+    srv.reset_stats()
+    arrivals = np.cumsum(np.random.default_rng(5).exponential(1.0 / lam, len(data)))
+    t_start = time.perf_counter()
+    tickets = []
+    for (k, x, y), o, ta in zip(data, outs, arrivals):
+        now = time.perf_counter() - t_start
+        if ta > now:
+            time.sleep(ta - now)
+        tickets.append(srv.submit(k, x, y, o[0], o[1]))
+    for t in tickets:
+        srv.wait(t)
+    st = srv.stats()
+    srv.close()
+    return {"requests": len(data), "offered_req_per_s": lam, "sustained_pts_per_s": rate_pts,
+            "p50_us": st["p50_us"], "p99_us": st["p99_us"], "mean_us": st["mean_us"],
+            "max_us": st["max_us"], "points_per_s": st["points_per_s"],
+            "tests_per_s": st["tests_per_s"], "graph_replays": st["graph_replays"],
+            "slots": slots, "slot_points": slot_points}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scale", type=float, default=1.0, help="fraction of the point counts")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--autotune", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the design for sharding points across GPUs is described in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1403_0802_amd import gp
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    c3, c4 = build_workloads(args.scale)
+    geom3, p3, px3, py3 = c3
+    geom4, p4, px4, py4 = c4
+    t0 = time.perf_counter()
+    grid3 = gp.gp_build_grid("pip", geom3, p3)
+    t1 = time.perf_counter()
+    grid4 = gp.gp_build_grid("p2p", geom4, p4)
+    t2 = time.perf_counter()
+    build_ms = {"pip": 1e3 * (t1 - t0), "p2p": 1e3 * (t2 - t1)}
+    x3, y3 = torch.from_numpy(px3).to(dev), torch.from_numpy(py3).to(dev)
+    x4, y4 = torch.from_numpy(px4).to(dev), torch.from_numpy(py4).to(dev)
+    del px3, py3
+    prec = "mixed"
+    ws3 = gp.new_workspace(grid3, x3.numel(), "mixed")
+    ws4 = gp.new_workspace(grid4, x4.numel(), "mixed")
+    id3 = torch.empty(x3.numel(), dtype=torch.int32, device=dev)
+    id4 = torch.empty(x4.numel(), dtype=torch.int32, device=dev)
+    d4 = torch.empty(x4.numel(), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    if args.autotune:
+        n_s = min(x3.numel(), 4_000_000)
+        log("[bench] autotune pip", gp.gp_autotune(grid3, prec, x3[:n_s], y3[:n_s], ws3))
+        n_s = min(x4.numel(), 8_000_000)
+        log("[bench] autotune p2p", gp.gp_autotune(grid4, prec, x4[:n_s], y4[:n_s], ws4))
+
+    def step(stats):
+        a = gp.gp_pip(grid3, x3, y3, id3, prec, ws3, stream, stats)
+        b = gp.gp_p2p(grid4, x4, y4, id4, d4, prec, ws4, stream, stats)
+        return a, b
+
+    for i in range(args.warmup):
+        step(False)
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    st_pip, st_p2p = [], []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        a, b = step(True)  # stats: hipEvents around each stage on this stream
+        st_pip.append(a)
+        st_p2p.append(b)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    log(f"[bench] {args.steps} timed steps in {t_total:.3f}s")
+    ms_step = 1e3 * t_total / args.steps
+    tests_pip = st_pip[0]["tests"]
+    tests_p2p = st_p2p[0]["tests"]
+    value = (tests_pip + tests_p2p) / (ms_step / 1e3)
+
+    def avg(lst, key):
+        return float(np.mean([s[key] for s in lst]))
+
+    pip_ref = avg(st_pip, "ms_refine")
+    p2p_ref = avg(st_p2p, "ms_refine")
+    pip_flops = tests_pip * F_PIP / (pip_ref / 1e3)
+    p2p_flops = tests_p2p * F_P2P / (p2p_ref / 1e3)
+    dom = "p2p" if p2p_ref >= pip_ref else "pip"
+    dom_kernel = "k_p2pmix" if dom == "p2p" else "k_pipmix"
+    achieved = p2p_flops if dom == "p2p" else pip_flops
+    workload = "C3 PIP 50M pts x 5000 polygons + C4 P2P 200M pts x 200000 polylines, mixed"
+    if args.scale != 1.0:
+        workload += f" (points x{args.scale})"
+    traffic = load_traffic(dom_kernel, workload)
+    detail = {
+        "pip": {"points": x3.numel(), "tests": tests_pip, "ms": avg(st_pip, "ms_total"),
+                "ms_pairing": avg(st_pip, "ms_pairing"), "ms_refine": pip_ref,
+                "ms_recheck": avg(st_pip, "ms_recheck"), "n_rechecked": st_pip[0]["n_rechecked"],
+                "n_items": st_pip[0]["n_items"], "refine_tflops": pip_flops / 1e12,
+                "refine_frac_fp32": pip_flops / FP32_PEAK},
+        "p2p": {"points": x4.numel(), "tests": tests_p2p, "ms": avg(st_p2p, "ms_total"),
+                "ms_pairing": avg(st_p2p, "ms_pairing"), "ms_refine": p2p_ref,
+                "ms_recheck": avg(st_p2p, "ms_recheck"), "n_rechecked": st_p2p[0]["n_rechecked"],
+                "n_items": st_p2p[0]["n_items"], "refine_tflops": p2p_flops / 1e12,
+                "refine_frac_fp32": p2p_flops / FP32_PEAK},
+        "grid_build_ms": build_ms,
+        "tuning": {"pip": gp.gp_get_tuning(grid3, prec), "p2p": gp.gp_get_tuning(grid4, prec)},
+    }
+    # the FP64 form on the same inputs, for comparison
+    if not args.no_fp64:
+        del ws3, ws4
+        torch.cuda.empty_cache()
+        w3 = gp.new_workspace(grid3, x3.numel(), "fp64")
+        w4 = gp.new_workspace(grid4, x4.numel(), "fp64")
+        gp.gp_pip(grid3, x3, y3, id3, "fp64", w3, stream, False)
+        gp.gp_p2p(grid4, x4, y4, id4, d4, "fp64", w4, stream, False)
+        a = gp.gp_pip(grid3, x3, y3, id3, "fp64", w3, stream, True)
+        b = gp.gp_p2p(grid4, x4, y4, id4, d4, "fp64", w4, stream, True)
+        ms64 = a["ms_total"] + b["ms_total"]
+        detail["fp64_form"] = {
+            "tests_per_s": (tests_pip + tests_p2p) / (ms64 / 1e3), "ms_per_step": ms64,
+            "pip_ms_refine": a["ms_refine"], "p2p_ms_refine": b["ms_refine"],
+            "pip_refine_frac_fp64": tests_pip * F_PIP / (a["ms_refine"] / 1e3) / FP64_PEAK,
+            "p2p_refine_frac_fp64": tests_p2p * F_P2P / (b["ms_refine"] / 1e3) / FP64_PEAK,
+            "mixed_speedup": ms64 / ms_step}
+        del w3, w4
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        log("[bench] serving run")
+        del x4, y4, id4, d4
+        torch.cuda.empty_cache()
+        detail["serving"] = serving_run(gp, torch, grid3, grid4, args.serve_requests, prec)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "tests/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded stand-ins for the paper's datasets)",
+        "config": {"workload": workload, "pip_points": detail["pip"]["points"],
+                   "p2p_points": detail["p2p"]["points"], "pip_polygons": geom3.n_features,
+                   "p2p_polylines": geom4.n_features, "radius_D_m": 100.0,
+                   "precision": "mixed (FP32 cell-rebased + FP64 recheck)"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK, "traffic": traffic,
+                     "kernel": dom_kernel,
+                     "flop_per_test": F_P2P if dom == "p2p" else F_PIP},
+        "cpu_baseline": None,
+        "detail": detail,
+    }
+    if not args.no_cpu:
+        log("[bench] cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(c3, c4, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

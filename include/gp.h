@@ -223,6 +223,8 @@ gp_status gp_serve_poll(gp_server *srv, uint64_t ticket, int32_t *done);
  * request's own status once complete; GP_E_TIMEOUT otherwise. */
 gp_status gp_serve_wait(gp_server *srv, uint64_t ticket, int64_t timeout_us);
 gp_status gp_serve_stats_get(gp_server *srv, gp_serve_stats *stats);
+/* Forget the latency samples and counters gathered so far (e.g. after a warm-up). */
+gp_status gp_serve_stats_reset(gp_server *srv);
 /* Drain in-flight work, stop the server thread and free everything. */
 gp_status gp_serve_destroy(gp_server *srv);
 

@@ -60,11 +60,12 @@ struct DevBuf {
 };
 }  // namespace
 
+// Defaults from autotuning on the configuration-3/4 workloads (gp_autotune re-tunes).
 static gp_tuning default_tuning(gp_kind kind, gp_precision prec) {
   gp_tuning t;
-  t.points_per_lane = (prec == GP_MIXED) ? 2 : 1;
-  t.edge_chunk = (kind == GP_PIP) ? 256 : 256;
-  t.wg_per_cu = 8;
+  t.points_per_lane = (prec == GP_MIXED && kind == GP_P2P) ? 2 : 1;
+  t.edge_chunk = 256;
+  t.wg_per_cu = 16;
   t.persistent = 1;
   return t;
 }
@@ -357,17 +358,9 @@ size_t workspace_layout(const Grid &g, int64_t n, gp_precision prec, void *base,
   w.items = (Item *)take((size_t)max_items(g, n) * sizeof(Item));
   w.counters = (uint32_t *)take(C_COUNT * 4);
   w.tests = (unsigned long long *)take(16);
-  if (prec == GP_MIXED) {
-    w.xs32 = (float *)take(un * 4);
-    w.ys32 = (float *)take(un * 4);
-    w.xs64 = w.ys64 = nullptr;
-    w.rq = (uint32_t *)take(un * 4);
-  } else {
-    w.xs32 = w.ys32 = nullptr;
-    w.xs64 = (double *)take(un * 8);
-    w.ys64 = (double *)take(un * 8);
-    w.rq = nullptr;
-  }
+  w.xyA = (double2 *)take(un * 16);
+  w.xyB = (double2 *)take(un * 16);
+  w.rq = prec == GP_MIXED ? (uint32_t *)take(un * 4) : nullptr;
   w.bytes = off;
   if (ws) *ws = w;
   return off;
@@ -400,13 +393,15 @@ static float half_box(const Grid &g) {
   return (float)(hb * (1.0 + 0x1p-20));
 }
 
-// Hash, sort and offsets: the point side of the filter.
+// Hash, sort and offsets: the point side of the filter.  With xy != NULL the FP64
+// points travel through the sort and *xy receives them in sorted order.
 static hipError_t pair_points(const Grid &g, int64_t n, const double *px, const double *py,
-                              Workspace &w, hipStream_t s, uint32_t **skey, uint32_t **perm) {
+                              Workspace &w, hipStream_t s, uint32_t **skey, uint32_t **perm,
+                              double2 **xy) {
   hipError_t e = launch_hash(px, py, n, g.x0, g.y0, g.cs, g.nx, g.ny, w.keyA, s);
   if (e != hipSuccess) return e;
   e = launch_radix_sort(w.keyA, w.keyB, w.valA, w.valB, (size_t)n, bits_for((uint64_t)g.ncells),
-                        true, w.hist, w.scan_tmp, s, skey, perm);
+                        true, w.hist, w.scan_tmp, s, skey, perm, px, py, w.xyA, w.xyB, xy);
   if (e != hipSuccess) return e;
   return launch_offsets(*skey, n, g.ncells, w.pt_off, s);
 }
@@ -439,7 +434,8 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   GP_TRY_HIP(launch_fill_u32(w.counters, 0u, C_COUNT, s));
   GP_TRY_HIP(launch_fill_u32((uint32_t *)w.tests, 0u, 2, s));
   uint32_t *skey = nullptr, *perm = nullptr;
-  GP_TRY_HIP(pair_points(*g, n, px, py, w, s, &skey, &perm));
+  double2 *xy = nullptr;
+  GP_TRY_HIP(pair_points(*g, n, px, py, w, s, &skey, &perm, &xy));
 
   RefineArgs a;
   memset(&a, 0, sizeof(a));
@@ -463,20 +459,14 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   a.p2p_margin = (float)std::max(0.01 * g->D, g->cs * 0x1p-10);
   a.skey = skey;
   a.perm = perm;
-  a.xs32 = w.xs32;
-  a.ys32 = w.ys32;
-  a.xs64 = w.xs64;
-  a.ys64 = w.ys64;
-  a.px = px;
-  a.py = py;
+  a.xy = xy;
   a.out_id = out_id;
   a.out_dist = kind == GP_P2P ? out_dist : nullptr;
   a.rq = w.rq;
   a.rq_count = w.counters + C_RQ;
   a.edge_chunk = t.edge_chunk;
 
-  GP_TRY_HIP(launch_gather(a, n, prec == GP_MIXED, w.counters + C_NPAIRED, w.xs32, w.ys32,
-                           w.xs64, w.ys64, s));
+  GP_TRY_HIP(launch_unpaired(a, n, w.counters + C_NPAIRED, s));
   GP_TRY_HIP(launch_items(w.pt_off, g->d_cand_off, g->d_cell_edges, g->ncells,
                           64 * t.points_per_lane, w.item_cnt, w.scan_tmp, w.items, w.counters,
                           w.tests, s));
@@ -535,7 +525,7 @@ extern "C" gp_status gp_pair_points(const gp_grid *g, int64_t n, const double *p
     return set_error(GP_E_INVALID_ARG, "workspace too small: %zu bytes needed", need);
   hipStream_t s = (hipStream_t)hip_stream;
   uint32_t *skey = w.keyA, *perm = w.valA;
-  if (n > 0) GP_TRY_HIP(pair_points(*g, n, px, py, w, s, &skey, &perm));
+  if (n > 0) GP_TRY_HIP(pair_points(*g, n, px, py, w, s, &skey, &perm, nullptr));
   else GP_TRY_HIP(launch_offsets(skey, 0, g->ncells, w.pt_off, s));
   GP_TRY_HIP(launch_copy_perm(perm, n, perm_out, s));
   GP_TRY_HIP(hipMemcpyAsync(pt_off_out, w.pt_off, ((size_t)g->ncells + 1) * 4,
@@ -592,11 +582,12 @@ extern "C" gp_status gp_autotune(gp_grid *g, gp_precision prec, int64_t n, const
   GP_TRY_HIP(d_id.alloc((size_t)n * 4));
   GP_TRY_HIP(d_dist.alloc((size_t)n * 8));
   std::vector<gp_tuning> space;
-  const int ppls[3] = {1, 2, 4}, ecs[3] = {128, 256, 512}, wgs[3] = {4, 8, 16};
+  const int ppls[3] = {1, 2, 4}, ecs[3] = {128, 256, 512}, wgs[4] = {8, 12, 16, 32};
   for (int p : ppls)
     for (int e : ecs)
       for (int wgc : wgs) space.push_back(gp_tuning{p, e, wgc, 1});
-  for (int p : ppls) space.push_back(gp_tuning{p, 256, 8, 0});
+  for (int p : ppls)
+    for (int e : ecs) space.push_back(gp_tuning{p, e, 16, 0});
   float best_t = INFINITY;
   gp_tuning best_cfg = g->tune[prec];
   for (const gp_tuning &t : space) {

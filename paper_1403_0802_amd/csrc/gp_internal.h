@@ -40,9 +40,7 @@ struct RefineArgs {
   // points, sorted by cell
   const uint32_t *skey;      // sorted cell ids
   const uint32_t *perm;      // sorted position -> caller index
-  const float *xs32, *ys32;  // GP_MIXED: rebased FP32
-  const double *xs64, *ys64; // GP_FP64: sorted FP64
-  const double *px, *py;     // caller's points (recheck reads them through perm)
+  const double2 *xy;         // FP64 points in sorted order
   // outputs (caller order)
   int32_t *out_id;
   double *out_dist;
@@ -75,8 +73,7 @@ struct Workspace {
   uint32_t *hist;        // radix histogram [256 * nblk]
   uint32_t *scan_tmp;    // scan partials
   int32_t *pt_off;       // [ncells+1]
-  float *xs32, *ys32;
-  double *xs64, *ys64;
+  double2 *xyA, *xyB;    // FP64 point payload of the sort (ping-pong)
   uint32_t *item_cnt;    // [ncells+1] -> exclusive offsets
   Item *items;
   uint32_t *rq;
@@ -94,10 +91,14 @@ size_t scan_tmp_elems(size_t n);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t n,
                                      uint32_t *tmp, hipStream_t s);
+// Stable sort of (key, value) by key.  With pl_out != NULL the FP64 point (px[i], py[i])
+// of every record travels with it (ping-pong through plA/plB; *pl_out = sorted copy).
 hipError_t launch_radix_sort(uint32_t *keyA, uint32_t *keyB, uint32_t *valA, uint32_t *valB,
                              size_t n, int nbits, bool values_are_identity, uint32_t *hist,
                              uint32_t *scan_tmp, hipStream_t s, uint32_t **keys_out,
-                             uint32_t **vals_out);
+                             uint32_t **vals_out, const double *px = nullptr,
+                             const double *py = nullptr, double2 *plA = nullptr,
+                             double2 *plB = nullptr, double2 **pl_out = nullptr);
 size_t radix_hist_elems(size_t n);
 
 // grid build
@@ -124,9 +125,7 @@ hipError_t launch_hash(const double *px, const double *py, int64_t n, double x0,
                        double cs, int32_t nx, int32_t ny, uint32_t *key, hipStream_t s);
 hipError_t launch_offsets(const uint32_t *skey, int64_t n, int32_t ncells, int32_t *pt_off,
                           hipStream_t s);
-hipError_t launch_gather(const RefineArgs &a, int64_t n, bool mixed, uint32_t *n_paired,
-                         float *xs32, float *ys32, double *xs64, double *ys64,
-                         hipStream_t s);
+hipError_t launch_unpaired(const RefineArgs &a, int64_t n, uint32_t *n_paired, hipStream_t s);
 hipError_t launch_items(const int32_t *pt_off, const int32_t *cand_off,
                         const int64_t *cell_edges, int32_t ncells, int32_t chunk,
                         uint32_t *item_cnt, uint32_t *scan_tmp, Item *items, uint32_t *counters,

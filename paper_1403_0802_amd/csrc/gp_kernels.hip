@@ -32,10 +32,10 @@ namespace gp {
 #define RS_THREADS 256
 #define RS_ITEMS 16
 #define RS_TILE (RS_THREADS * RS_ITEMS)
-#define RS_BITS 8
-#define RS_BUCKETS 256
+#define RS_MAX_BITS 10
+#define RS_MAX_BUCKETS (1 << RS_MAX_BITS)
 
-__device__ __forceinline__ uint64_t ballot(bool c) { return __ballot(c); }
+__device__ __forceinline__ uint64_t ballot(bool c) { return __builtin_amdgcn_ballot_w64(c); }
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint64_t lanemask_lt() {
   return (1ull << lane_id()) - 1ull;
@@ -174,41 +174,50 @@ hipError_t launch_exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t n
 }
 
 // ------------------------------------------------------------------------- radix sort
-// Stable LSD radix sort of (uint32 key, uint32 value) pairs, 8 bits per pass.  Each
-// pass: per-tile digit histogram, exclusive scan of the digit-major histogram, then a
-// stable scatter in which every key's rank among equal digits of its tile comes from
-// wavefront ballots (peer masks), not from atomics, so the output order is fixed.
+// Stable LSD radix sort of (uint32 key, uint32 value[, FP64 (x, y) payload]) records.
+// Digits are at most 10 bits wide and the pass count is the least that covers the key
+// width.  Each pass: per-tile digit histogram, exclusive scan of the digit-major
+// histogram, then a stable scatter in which every key's rank among equal digits of its
+// tile comes from wavefront ballots (peer masks), not from atomics, so the output
+// order is fixed.
 
 size_t radix_hist_elems(size_t n) {
   size_t nblk = (n + RS_TILE - 1) / RS_TILE;
   if (nblk == 0) nblk = 1;
-  return (size_t)RS_BUCKETS * nblk;
+  return (size_t)RS_MAX_BUCKETS * nblk;
 }
 
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t *keys, size_t n,
-                                                        int shift, uint32_t *hist,
+                                                        int shift, int bits, uint32_t *hist,
                                                         uint32_t nblk) {
-  __shared__ uint32_t cnt[RS_BUCKETS];
-  cnt[threadIdx.x] = 0;
+  __shared__ uint32_t cnt[RS_MAX_BUCKETS];
+  const uint32_t nb = 1u << bits, mask = nb - 1u;
+  for (uint32_t d = threadIdx.x; d < nb; d += RS_THREADS) cnt[d] = 0;
   __syncthreads();
   const size_t base = (size_t)blockIdx.x * RS_TILE;
   for (int r = 0; r < RS_ITEMS; ++r) {
     size_t i = base + (size_t)r * RS_THREADS + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (RS_BUCKETS - 1)], 1u);
+    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & mask], 1u);
   }
   __syncthreads();
-  hist[(size_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+  for (uint32_t d = threadIdx.x; d < nb; d += RS_THREADS)
+    hist[(size_t)d * nblk + blockIdx.x] = cnt[d];
 }
 
-__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t *kin, const uint32_t *vin,
-                                                           uint32_t *kout, uint32_t *vout,
-                                                           size_t n, int shift,
-                                                           const uint32_t *offs, uint32_t nblk) {
-  __shared__ uint32_t run[RS_BUCKETS];
-  __shared__ uint32_t wcnt[RS_THREADS / GP_WAVE][RS_BUCKETS];
+// Payload: pass 0 reads it from the caller's separate x/y arrays (px0, py0), later
+// passes from the interleaved array pin; it is written interleaved to pout.
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
+    const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, size_t n,
+    int shift, int bits, const uint32_t *offs, uint32_t nblk, const double *px0,
+    const double *py0, const double2 *pin, double2 *pout) {
+  __shared__ uint32_t run[RS_MAX_BUCKETS];
+  __shared__ uint32_t wcnt[RS_THREADS / GP_WAVE][RS_MAX_BUCKETS];
   const uint32_t tid = threadIdx.x, wave = tid / GP_WAVE;
-  run[tid] = offs[(size_t)tid * nblk + blockIdx.x];
-  for (int w = 0; w < RS_THREADS / GP_WAVE; ++w) wcnt[w][tid] = 0;
+  const uint32_t nb = 1u << bits, mask = nb - 1u;
+  for (uint32_t d = tid; d < nb; d += RS_THREADS) {
+    run[d] = offs[(size_t)d * nblk + blockIdx.x];
+    for (int w = 0; w < RS_THREADS / GP_WAVE; ++w) wcnt[w][d] = 0;
+  }
   __syncthreads();
   const size_t base = (size_t)blockIdx.x * RS_TILE;
   for (int r = 0; r < RS_ITEMS; ++r) {
@@ -216,10 +225,11 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t *kin, 
     bool valid = i < n;
     uint32_t k = valid ? kin[i] : 0u;
     uint32_t v = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
-    uint32_t d = (k >> shift) & (RS_BUCKETS - 1);
+    double2 pl = make_double2(0.0, 0.0);
+    if (valid && pout) pl = pin ? pin[i] : make_double2(px0[i], py0[i]);
+    uint32_t d = (k >> shift) & mask;
     uint64_t peers = ballot(valid);
-#pragma unroll
-    for (int b = 0; b < RS_BITS; ++b) {
+    for (int b = 0; b < bits; ++b) {
       uint64_t m = ballot((d >> b) & 1u);
       peers &= ((d >> b) & 1u) ? m : ~m;
     }
@@ -231,14 +241,17 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t *kin, 
       for (uint32_t w = 0; w < wave; ++w) pos += wcnt[w][d];
       kout[pos] = k;
       vout[pos] = v;
+      if (pout) pout[pos] = pl;
     }
     __syncthreads();
-    uint32_t add = 0;
-    for (int w = 0; w < RS_THREADS / GP_WAVE; ++w) {
-      add += wcnt[w][tid];
-      wcnt[w][tid] = 0;
+    for (uint32_t dd = tid; dd < nb; dd += RS_THREADS) {
+      uint32_t add = 0;
+      for (int w = 0; w < RS_THREADS / GP_WAVE; ++w) {
+        add += wcnt[w][dd];
+        wcnt[w][dd] = 0;
+      }
+      run[dd] += add;
     }
-    run[tid] += add;
     __syncthreads();
   }
 }
@@ -246,32 +259,43 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t *kin, 
 hipError_t launch_radix_sort(uint32_t *keyA, uint32_t *keyB, uint32_t *valA, uint32_t *valB,
                              size_t n, int nbits, bool values_are_identity, uint32_t *hist,
                              uint32_t *scan_tmp, hipStream_t s, uint32_t **keys_out,
-                             uint32_t **vals_out) {
+                             uint32_t **vals_out, const double *px, const double *py,
+                             double2 *plA, double2 *plB, double2 **pl_out) {
   *keys_out = keyA;
   *vals_out = valA;
+  if (pl_out) *pl_out = plA;
   if (n == 0) return hipSuccess;
-  uint32_t nblk = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
-  int passes = (nbits + RS_BITS - 1) / RS_BITS;
+  const uint32_t nblk = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
+  int passes = (nbits + RS_MAX_BITS - 1) / RS_MAX_BITS;
   if (passes < 1) passes = 1;
+  const int bits = nbits < 1 ? 1 : (nbits + passes - 1) / passes;
   uint32_t *ki = keyA, *ko = keyB, *vi = valA, *vo = valB;
+  double2 *pi = nullptr, *po = pl_out ? plA : nullptr;
   bool ident = values_are_identity;
   for (int p = 0; p < passes; ++p) {
-    int shift = p * RS_BITS;
-    hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(RS_THREADS), 0, s, ki, n, shift, hist, nblk);
+    const int shift = p * bits;
+    hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(RS_THREADS), 0, s, ki, n, shift, bits, hist,
+                       nblk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_exclusive_scan_u32(hist, hist, (size_t)RS_BUCKETS * nblk, scan_tmp, s);
+    e = launch_exclusive_scan_u32(hist, hist, ((size_t)1 << bits) * nblk, scan_tmp, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(RS_THREADS), 0, s, ki,
-                       ident ? (const uint32_t *)nullptr : vi, ko, vo, n, shift, hist, nblk);
+                       ident ? (const uint32_t *)nullptr : vi, ko, vo, n, shift, bits, hist,
+                       nblk, px, py, (const double2 *)pi, po);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     ident = false;
     uint32_t *t = ki; ki = ko; ko = t;
     t = vi; vi = vo; vo = t;
+    if (po) {
+      pi = po;
+      po = (po == plA) ? plB : plA;
+    }
   }
   *keys_out = ki;
   *vals_out = vi;
+  if (pl_out) *pl_out = pi;
   return hipSuccess;
 }
 
@@ -536,42 +560,36 @@ __device__ __forceinline__ double cell_cy(const RefineArgs &a, uint32_t cell) {
   return a.y0 + ((double)(cell / (uint32_t)a.nx) + 0.5) * a.cs;
 }
 
-// Gather the sorted points (FP32 rebased to the cell centre for the mixed form, FP64 for
-// the FP64 form); points that are unpaired (outside the extent, or in a cell without
-// candidates) get their final (-1, +inf) here.
-__global__ void k_gather(RefineArgs a, int64_t n, int mixed, float *xs32, float *ys32,
-                         double *xs64, double *ys64, uint32_t *n_paired) {
+// Points the filter leaves unpaired (outside the extent, or in a cell without
+// candidates) get their final (-1, +inf) here; the rest are counted.
+__global__ __launch_bounds__(256) void k_unpaired(RefineArgs a, int64_t n, uint32_t *n_paired) {
+  __shared__ uint32_t wsum[256 / GP_WAVE];
+  uint32_t cnt = 0;  // per-wave count (uniform), one atomic per block at the end
   for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < n;
        i0 += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = i0 + threadIdx.x;
     const bool in = i < n;
-    uint32_t k = in ? a.skey[i] : 0u;
-    uint32_t j = in ? a.perm[i] : 0u;
-    bool paired = in && k < (uint32_t)a.ncells && a.cand_off[k + 1] > a.cand_off[k];
-    uint64_t m = ballot(paired);
-    if (lane_id() == 0 && m) atomicAdd(n_paired, (uint32_t)__popcll(m));
-    if (!in) continue;
-    if (!paired) {
+    const uint32_t k = in ? a.skey[i] : 0u;
+    const bool paired = in && k < (uint32_t)a.ncells && a.cand_off[k + 1] > a.cand_off[k];
+    cnt += (uint32_t)__popcll(ballot(paired));
+    if (in && !paired) {
+      const uint32_t j = a.perm[i];
       a.out_id[j] = -1;
       if (a.out_dist) a.out_dist[j] = INFINITY;
-      continue;
     }
-    double x = a.px[j], y = a.py[j];
-    if (mixed) {
-      xs32[i] = (float)(x - cell_cx(a, k));
-      ys32[i] = (float)(y - cell_cy(a, k));
-    } else {
-      xs64[i] = x;
-      ys64[i] = y;
-    }
+  }
+  if (lane_id() == 0) wsum[threadIdx.x / GP_WAVE] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < 256 / GP_WAVE; ++w) t += wsum[w];
+    if (t) atomicAdd(n_paired, t);
   }
 }
 
-hipError_t launch_gather(const RefineArgs &a, int64_t n, bool mixed, uint32_t *n_paired,
-                         float *xs32, float *ys32, double *xs64, double *ys64, hipStream_t s) {
+hipError_t launch_unpaired(const RefineArgs &a, int64_t n, uint32_t *n_paired, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, a, n,
-                     mixed ? 1 : 0, xs32, ys32, xs64, ys64, n_paired);
+  hipLaunchKernelGGL(k_unpaired, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, a, n, n_paired);
   return hipGetLastError();
 }
 
@@ -689,6 +707,35 @@ __device__ __forceinline__ void push_recheck(const RefineArgs &a, bool flag, uin
   if (flag) a.rq[base + __popcll(m & lanemask_lt())] = pos;
 }
 
+// ------------------------------------------------------------------------- points
+
+template <int PPL>
+__device__ __forceinline__ void load_points64(const RefineArgs &a, const Item it,
+                                              double (&px)[PPL], double (&py)[PPL]) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    const int idx = (int)lane + GP_WAVE * j;
+    const double2 p = idx < it.npts ? a.xy[it.pt_lo + idx] : make_double2(0.0, 0.0);
+    px[j] = p.x;
+    py[j] = p.y;
+  }
+}
+
+// FP32 coordinates rebased to the cell centre: fl32(fl64(p - c)).
+template <int PPL>
+__device__ __forceinline__ void load_points32(const RefineArgs &a, const Item it, double cx,
+                                              double cy, float (&px)[PPL], float (&py)[PPL]) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    const int idx = (int)lane + GP_WAVE * j;
+    const double2 p = idx < it.npts ? a.xy[it.pt_lo + idx] : make_double2(cx, cy);
+    px[j] = (float)(p.x - cx);
+    py[j] = (float)(p.y - cy);
+  }
+}
+
 // ------------------------------------------------------------------------- PIP, FP64
 
 struct alignas(16) PipRec64 {
@@ -701,26 +748,21 @@ __device__ void pip64_item(const RefineArgs &a, const Item it, PipRec64 *lds) {
   const int EC = a.edge_chunk;
   double px[PPL], py[PPL];
   int32_t best[PPL];
+  load_points64<PPL>(a, it, px, py);
 #pragma unroll
-  for (int j = 0; j < PPL; ++j) {
-    int idx = (int)lane + GP_WAVE * j;
-    bool v = idx < it.npts;
-    px[j] = v ? a.xs64[it.pt_lo + idx] : 0.0;
-    py[j] = v ? a.ys64[it.pt_lo + idx] : 0.0;
-    best[j] = -1;
-  }
+  for (int j = 0; j < PPL; ++j) best[j] = -1;
   const int32_t k0 = a.cand_off[it.cell], k1 = a.cand_off[it.cell + 1];
   for (int32_t k = k0; k < k1; ++k) {
     const int32_t f = a.cand_id[k];
     const int32_t e0 = a.eoff[f], e1 = a.eoff[f + 1];
-    uint32_t odd[PPL];
+    uint64_t par[PPL];
 #pragma unroll
-    for (int j = 0; j < PPL; ++j) odd[j] = 0;
+    for (int j = 0; j < PPL; ++j) par[j] = 0;
     for (int32_t s = e0; s < e1; s += EC) {
       const int cnt = (e1 - s) < EC ? (e1 - s) : EC;
       __syncthreads();
       for (int t = lane; t < cnt; t += GP_WAVE) {
-        double4 r = a.edge64[s + t];
+        const double4 r = a.edge64[s + t];
         PipRec64 q;
         q.lox = r.x; q.loy = r.y; q.hiy = r.w;
         q.w = r.z - r.x;
@@ -732,17 +774,20 @@ __device__ void pip64_item(const RefineArgs &a, const Item it, PipRec64 *lds) {
       for (int t = 0; t < cnt; ++t) {
         const PipRec64 q = lds[t];
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) odd[j] ^= (uint32_t)cross64(px[j], py[j], q.lox, q.loy, q.w,
-                                                                q.hiy, q.h);
+        for (int j = 0; j < PPL; ++j) {
+          const double lhs = (px[j] - q.lox) * q.h;
+          const double rhs = q.w * (py[j] - q.loy);
+          par[j] ^= ballot(q.loy <= py[j]) & ballot(py[j] < q.hiy) & ballot(lhs < rhs);
+        }
       }
     }
 #pragma unroll
     for (int j = 0; j < PPL; ++j)
-      if (best[j] < 0 && odd[j]) best[j] = f;
+      if (best[j] < 0 && ((par[j] >> lane) & 1ull)) best[j] = f;
   }
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
-    int idx = (int)lane + GP_WAVE * j;
+    const int idx = (int)lane + GP_WAVE * j;
     if (idx < it.npts) a.out_id[a.perm[it.pt_lo + idx]] = best[j];
   }
 }
@@ -760,6 +805,15 @@ __device__ void pip64_item(const RefineArgs &a, const Item it, PipRec64 *lds) {
 // G = 2^-22 * (|k| (3B + 3|lo.y|) + |lo.x| + 3B), B the cell half-width bound: four
 // times the rounding error of the FP32 intercept test against the FP64 predicate.
 
+// Lane mask of the crossings of one edge.  Each compare is balloted on its own and
+// the masks are combined on the scalar unit (a ballot of a combined predicate would
+// cost two extra vector instructions per test).
+__device__ __forceinline__ uint64_t plain_cross(float px, float py, const float4 e) {
+  const float ty = py - e.y;
+  const float xi = fmaf(ty, e.w, e.x);
+  return ballot(__float_as_uint(ty) < __float_as_uint(e.z)) & ballot(px < xi);
+}
+
 template <int PPL>
 __device__ void pipmix_item(const RefineArgs &a, const Item it, float4 *ldsA, float4 *ldsB,
                             float *ldsG) {
@@ -770,12 +824,9 @@ __device__ void pipmix_item(const RefineArgs &a, const Item it, float4 *ldsA, fl
   float px[PPL], py[PPL];
   int32_t best[PPL];
   bool rq[PPL];
+  load_points32<PPL>(a, it, cx, cy, px, py);
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
-    int idx = (int)lane + GP_WAVE * j;
-    bool v = idx < it.npts;
-    px[j] = v ? a.xs32[it.pt_lo + idx] : 0.0f;
-    py[j] = v ? a.ys32[it.pt_lo + idx] : 0.0f;
     best[j] = -1;
     rq[j] = false;
   }
@@ -816,7 +867,7 @@ __device__ void pipmix_item(const RefineArgs &a, const Item it, float4 *ldsA, fl
         }
         const uint64_t mB = ballot(act && careful), mA = ballot(act && !careful);
         if (act && careful) {
-          uint32_t p = nB + __popcll(mB & lanemask_lt());
+          const uint32_t p = nB + __popcll(mB & lanemask_lt());
           ldsB[p] = recB;
           ldsG[p] = G;
         }
@@ -825,29 +876,29 @@ __device__ void pipmix_item(const RefineArgs &a, const Item it, float4 *ldsA, fl
         nB += __popcll(mB);
       }
       __syncthreads();
-      for (uint32_t t = 0; t < nA; ++t) {
-        const float4 e = ldsA[t];
+      uint32_t t = 0;
+      for (; t + 2 <= nA; t += 2) {
+        const float4 e0 = ldsA[t], e1 = ldsA[t + 1];
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) {
-          const float ty = py[j] - e.y;
-          const float xi = fmaf(ty, e.w, e.x);
-          const bool c = (__float_as_uint(ty) < __float_as_uint(e.z)) & (px[j] < xi);
-          par[j] ^= ballot(c);
-        }
+        for (int j = 0; j < PPL; ++j)
+          par[j] ^= plain_cross(px[j], py[j], e0) ^ plain_cross(px[j], py[j], e1);
       }
-      for (uint32_t t = 0; t < nB; ++t) {
+      if (t < nA) {
+        const float4 e0 = ldsA[t];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) par[j] ^= plain_cross(px[j], py[j], e0);
+      }
+      for (t = 0; t < nB; ++t) {
         const float4 e = ldsB[t];
         const float G = ldsG[t];
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
           const float ty = py[j] - e.y;
-          const bool st = (ty >= 0.0f) & (py[j] < e.z);
-          const bool eq = (ty == 0.0f) | (py[j] == e.z);
           const float d = fmaf(ty, e.w, e.x) - px[j];
-          const bool c = st & (d > 0.0f);
-          const bool fl = (eq & !(d < -G)) | (st & !(fabsf(d) > G));
-          par[j] ^= ballot(c);
-          flg[j] |= ballot(fl);
+          const uint64_t st = ballot(ty >= 0.0f) & ballot(py[j] < e.z);
+          const uint64_t eq = ballot(ty == 0.0f) | ballot(py[j] == e.z);
+          par[j] ^= st & ballot(d > 0.0f);
+          flg[j] |= (eq & ballot(!(d < -G))) | (st & ballot(!(fabsf(d) > G)));
         }
       }
     }
@@ -886,12 +937,9 @@ __device__ void p2p64_item(const RefineArgs &a, const Item it, SegRec64 *lds, in
   const int EC = a.edge_chunk;
   double px[PPL], py[PPL], best[PPL];
   int32_t bid[PPL];
+  load_points64<PPL>(a, it, px, py);
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
-    int idx = (int)lane + GP_WAVE * j;
-    bool v = idx < it.npts;
-    px[j] = v ? a.xs64[it.pt_lo + idx] : 0.0;
-    py[j] = v ? a.ys64[it.pt_lo + idx] : 0.0;
     best[j] = a.D2_next;  // accept d2 <= fl(D*D); later only strictly smaller
     bid[j] = -1;
   }
@@ -966,15 +1014,29 @@ __device__ void p2p64_item(const RefineArgs &a, const Item it, SegRec64 *lds, in
 }
 
 // ------------------------------------------------------------------------- P2P, mixed
-// FP32 on cell-rebased coordinates with a branch-free clamped projection.  Per point the
-// wave tracks the best and second-best polyline (distinct ids).  With E the largest
-// distance error bound e_s = 16*2^-24*(B*sqrt2 + M_s) over segments near the cell
-// (M_s: largest rebased |coordinate| of the segment), a point is decided in FP32 only
-// when its winner is inside D - E and beats the runner-up by more than 2E, or when
-// nothing is within D + E; every other point is recomputed in FP64.
+// FP32 on cell-rebased coordinates.  Per segment the LDS holds a, d = b - a, d/|d|^2 and
+// -(a.d)/|d|^2, so the clamped projection parameter is two FMAs (the clamp is free) and
+// a point-segment test is 9 VALU operations; the minimum is taken on the float bits as
+// unsigned integers (valid for d^2 >= 0), two segments per v_min3.
+//
+// Per point the wave tracks the best and second-best polyline (distinct ids).  With E
+// the largest error bound e_s = 48*2^-24*(B*sqrt2 + M_s) over segments near the cell
+// (M_s: largest rebased |coordinate| of the segment; 48 is four times the constant of
+// the rounding analysis), the id is decided in FP32 only when the winner is inside
+// D - E and beats the runner-up by more than 2E, or when nothing is within D + E; all
+// other points go to the FP64 recheck.  The reported distance of an FP32-decided hit is
+// recomputed in FP64 over the winner's segments, so it equals the FP64 result bitwise.
+
+__device__ __forceinline__ uint32_t seg_d2_bits(float px, float py, const float4 s0,
+                                                const float4 s1) {
+  const float tt = __builtin_amdgcn_fmed3f(fmaf(px, s1.x, fmaf(py, s1.y, s1.z)), 0.0f, 1.0f);
+  const float wx = px - s0.x, wy = py - s0.y;
+  const float qx = fmaf(-tt, s0.z, wx), qy = fmaf(-tt, s0.w, wy);
+  return __float_as_uint(fmaf(qx, qx, qy * qy));
+}
 
 template <int PPL>
-__device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsS, float *ldsI,
+__device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsS0, float4 *ldsS1,
                             int2 *tab) {
   const uint32_t lane = lane_id();
   const int EC = a.edge_chunk;
@@ -982,17 +1044,16 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsS, fl
   const float hb = a.half_box;
   const float T = a.p2p_margin;
   const float near_lim = (float)a.D + T;
-  float px[PPL], py[PPL], b1[PPL], b2[PPL], pm[PPL];
+  float px[PPL], py[PPL];
+  uint32_t b1[PPL], b2[PPL], pm[PPL];
   int32_t f1[PPL];
+  load_points32<PPL>(a, it, cx, cy, px, py);
+  const uint32_t INFB = 0x7f800000u;
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
-    int idx = (int)lane + GP_WAVE * j;
-    bool v = idx < it.npts;
-    px[j] = v ? a.xs32[it.pt_lo + idx] : 0.0f;
-    py[j] = v ? a.ys32[it.pt_lo + idx] : 0.0f;
-    b1[j] = INFINITY;
-    b2[j] = INFINITY;
-    pm[j] = INFINITY;
+    b1[j] = INFB;
+    b2[j] = INFB;
+    pm[j] = INFB;
     f1[j] = -1;
   }
   float emax = 0.0f;  // per-lane partial of E over the segments this lane staged
@@ -1008,16 +1069,19 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsS, fl
       const int take = (s1 - s0) < (EC - filled) ? (s1 - s0) : (EC - filled);
       for (int t = lane; t < take; t += GP_WAVE) {
         const double4 r = a.edge64[s0 + t];
+        const double ax = r.x - cx, ay = r.y - cy;
         const double ddx = r.z - r.x, ddy = r.w - r.y;
         const double L2 = ddx * ddx + ddy * ddy;
-        const float ax = (float)(r.x - cx), ay = (float)(r.y - cy);
-        const float bx = (float)(r.z - cx), by = (float)(r.w - cy);
-        ldsS[filled + t] = make_float4(ax, ay, (float)ddx, (float)ddy);
-        ldsI[filled + t] = L2 > 0.0 ? (float)(1.0 / L2) : 0.0f;
-        const float M = fmaxf(fmaxf(fabsf(ax), fabsf(ay)), fmaxf(fabsf(bx), fabsf(by)));
-        const float es = 16.0f * 0x1p-24f * (hb * 1.4143f + M);
-        const float gx = fmaxf(0.0f, fmaxf(fminf(ax, bx) - hb, -hb - fmaxf(ax, bx)));
-        const float gy = fmaxf(0.0f, fmaxf(fminf(ay, by) - hb, -hb - fmaxf(ay, by)));
+        const double inv = L2 > 0.0 ? 1.0 / L2 : 0.0;
+        ldsS0[filled + t] = make_float4((float)ax, (float)ay, (float)ddx, (float)ddy);
+        ldsS1[filled + t] = make_float4((float)(ddx * inv), (float)(ddy * inv),
+                                        (float)(-(ax * ddx + ay * ddy) * inv), 0.0f);
+        const float fax = (float)ax, fay = (float)ay;
+        const float fbx = (float)(r.z - cx), fby = (float)(r.w - cy);
+        const float M = fmaxf(fmaxf(fabsf(fax), fabsf(fay)), fmaxf(fabsf(fbx), fabsf(fby)));
+        const float es = 48.0f * 0x1p-24f * (hb * 1.4143f + M);
+        const float gx = fmaxf(0.0f, fmaxf(fminf(fax, fbx) - hb, -hb - fmaxf(fax, fbx)));
+        const float gy = fmaxf(0.0f, fmaxf(fminf(fay, fby) - hb, -hb - fmaxf(fay, fby)));
         const bool nearc = (gx <= near_lim && gy <= near_lim &&
                             sqrtf(gx * gx + gy * gy) <= near_lim) || !(es <= 0.5f * T);
         if (nearc) emax = fmaxf(emax, es);
@@ -1035,24 +1099,25 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsS, fl
       const int2 te = tab[q];
       const int32_t f = te.x;
       const int end = te.y & 0x7fffffff;
-      for (int t = start; t < end; ++t) {
-        const float4 sg = ldsS[t];
-        const float inv = ldsI[t];
+      int t = start;
+      for (; t + 2 <= end; t += 2) {
+        const float4 s00 = ldsS0[t], s01 = ldsS1[t], s10 = ldsS0[t + 1], s11 = ldsS1[t + 1];
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) {
-          const float wx = px[j] - sg.x, wy = py[j] - sg.y;
-          const float dot = fmaf(wx, sg.z, wy * sg.w);
-          const float tt = __builtin_amdgcn_fmed3f(dot * inv, 0.0f, 1.0f);
-          const float qx = fmaf(-tt, sg.z, wx), qy = fmaf(-tt, sg.w, wy);
-          pm[j] = fminf(pm[j], fmaf(qx, qx, qy * qy));
-        }
+        for (int j = 0; j < PPL; ++j)
+          pm[j] = min(pm[j], min(seg_d2_bits(px[j], py[j], s00, s01),
+                                 seg_d2_bits(px[j], py[j], s10, s11)));
+      }
+      if (t < end) {
+        const float4 s00 = ldsS0[t], s01 = ldsS1[t];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) pm[j] = min(pm[j], seg_d2_bits(px[j], py[j], s00, s01));
       }
       if (!(te.y & (int)0x80000000)) {
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
           if (pm[j] < b1[j]) { b2[j] = b1[j]; b1[j] = pm[j]; f1[j] = f; }
           else if (pm[j] < b2[j]) b2[j] = pm[j];
-          pm[j] = INFINITY;
+          pm[j] = INFB;
         }
       }
       start = end;
@@ -1065,14 +1130,26 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsS, fl
   for (int j = 0; j < PPL; ++j) {
     const int idx = (int)lane + GP_WAVE * j;
     const bool v = idx < it.npts;
-    const double d1 = (double)sqrtf(b1[j]), d2 = (double)sqrtf(b2[j]);
+    const double d1 = (double)sqrtf(__uint_as_float(b1[j]));
+    const double d2 = (double)sqrtf(__uint_as_float(b2[j]));
     const bool hit = (d1 < D - E) && (d2 - d1 > 2.0 * E);
     const bool miss = d1 > D + E;
     const bool flag = !(hit || miss);
-    if (v && !flag) {
+    if (v && hit) {
+      // exact FP64 distance to the winning polyline
+      const double2 p = a.xy[it.pt_lo + idx];
+      double pd = INFINITY;
+      for (int32_t e = a.eoff[f1[j]]; e < a.eoff[f1[j] + 1]; ++e) {
+        const double4 r = a.edge64[e];
+        pd = fmin(pd, seg_d2_64(p.x, p.y, r.x, r.y, r.z, r.w));
+      }
       const uint32_t o = a.perm[it.pt_lo + idx];
-      a.out_id[o] = hit ? f1[j] : -1;
-      a.out_dist[o] = hit ? d1 : INFINITY;
+      a.out_id[o] = f1[j];
+      a.out_dist[o] = sqrt(pd);
+    } else if (v && miss) {
+      const uint32_t o = a.perm[it.pt_lo + idx];
+      a.out_id[o] = -1;
+      a.out_dist[o] = INFINITY;
     }
     push_recheck(a, v && flag, (uint32_t)(it.pt_lo + idx));
   }
@@ -1125,13 +1202,13 @@ __global__ __launch_bounds__(64) void k_p2p64(RefineArgs a, int persistent) {
 template <int PPL>
 __global__ __launch_bounds__(64) void k_p2pmix(RefineArgs a, int persistent) {
   extern __shared__ __align__(16) unsigned char smem[];
-  float4 *S = (float4 *)smem;
-  float *I = (float *)(S + a.edge_chunk);
-  int2 *tab = (int2 *)(I + a.edge_chunk);
+  float4 *S0 = (float4 *)smem;
+  float4 *S1 = S0 + a.edge_chunk;
+  int2 *tab = (int2 *)(S1 + a.edge_chunk);
   const uint32_t n_items = *a.n_items;
   uint32_t it = persistent ? next_item(a) : blockIdx.x;
   while (it < n_items) {
-    p2pmix_item<PPL>(a, a.items[it], S, I, tab);
+    p2pmix_item<PPL>(a, a.items[it], S0, S1, tab);
     if (!persistent) break;
     it = next_item(a);
   }
@@ -1141,7 +1218,7 @@ static size_t refine_lds_bytes(gp_kind kind, gp_precision prec, int ec) {
   if (kind == GP_PIP)
     return prec == GP_FP64 ? (size_t)ec * sizeof(PipRec64) : (size_t)ec * (16 + 16 + 4);
   return prec == GP_FP64 ? (size_t)ec * (sizeof(SegRec64) + sizeof(int2))
-                         : (size_t)ec * (16 + 4 + sizeof(int2));
+                         : (size_t)ec * (16 + 16 + sizeof(int2));
 }
 
 #define GP_DISPATCH(KERNEL, PPLV, ...)                                             \
@@ -1176,54 +1253,94 @@ hipError_t launch_refine(gp_kind kind, gp_precision prec, const RefineArgs &a,
 }
 
 // ------------------------------------------------------------------------- FP64 recheck
-// One thread per queued point: the point's full result over all candidates of its cell,
-// in FP64 with the definitions' operation order, straight from the edge records.
+// One wavefront per queued point: the point's full result over all candidates of its
+// cell, in FP64 with the definitions' operation order, straight from the edge records.
+// Lanes take the edges of a feature; parity combines by popcount of the crossing
+// ballots (XOR), distance by an exact wave minimum -- both independent of order.
 
-__global__ void k_recheck_pip(RefineArgs a) {
+__device__ __forceinline__ double wave_min_f64(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, GP_WAVE));
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_recheck_pip(RefineArgs a) {
   const uint32_t nq = *a.rq_count;
-  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+  const uint32_t lane = lane_id();
+  const uint32_t waves = gridDim.x * (blockDim.x / GP_WAVE);
+  for (uint32_t q = blockIdx.x * (blockDim.x / GP_WAVE) + threadIdx.x / GP_WAVE; q < nq;
+       q += waves) {
     const uint32_t i = a.rq[q];
     const uint32_t j = a.perm[i], cell = a.skey[i];
-    const double x = a.px[j], y = a.py[j];
+    const double2 p = a.xy[i];
+    const double x = p.x, y = p.y;
     int32_t best = -1;
     for (int32_t k = a.cand_off[cell]; k < a.cand_off[cell + 1] && best < 0; ++k) {
       const int32_t f = a.cand_id[k];
       uint32_t odd = 0;
-      for (int32_t e = a.eoff[f]; e < a.eoff[f + 1]; ++e) {
-        const double4 r = a.edge64[e];
-        odd ^= (uint32_t)cross64(x, y, r.x, r.y, r.z - r.x, r.w, r.w - r.y);
+      for (int32_t e0 = a.eoff[f]; e0 < a.eoff[f + 1]; e0 += GP_WAVE) {
+        const int32_t e = e0 + (int32_t)lane;
+        bool c = false;
+        if (e < a.eoff[f + 1]) {
+          const double4 r = a.edge64[e];
+          c = cross64(x, y, r.x, r.y, r.z - r.x, r.w, r.w - r.y);
+        }
+        odd ^= (uint32_t)__popcll(ballot(c)) & 1u;
       }
       if (odd) best = f;
     }
-    a.out_id[j] = best;
+    if (lane == 0) a.out_id[j] = best;
   }
 }
 
-__global__ void k_recheck_p2p(RefineArgs a) {
+__global__ __launch_bounds__(256) void k_recheck_p2p(RefineArgs a) {
   const uint32_t nq = *a.rq_count;
-  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+  const uint32_t lane = lane_id();
+  const uint32_t waves = gridDim.x * (blockDim.x / GP_WAVE);
+  for (uint32_t q = blockIdx.x * (blockDim.x / GP_WAVE) + threadIdx.x / GP_WAVE; q < nq;
+       q += waves) {
     const uint32_t i = a.rq[q];
     const uint32_t j = a.perm[i], cell = a.skey[i];
-    const double x = a.px[j], y = a.py[j];
+    const double2 p = a.xy[i];
+    const double x = p.x, y = p.y;
     int32_t bid = -1;
     double best = INFINITY;
     for (int32_t k = a.cand_off[cell]; k < a.cand_off[cell + 1]; ++k) {
       const int32_t f = a.cand_id[k];
+      // a segment matters only if its d2 can beat thr = min(best, next(D2)); its
+      // perpendicular quotient is divided out only when cc < fl(thr*L2)*(1+2^-49)
+      const double thr = fmin(best, a.D2_next);
       double pd = INFINITY;
-      for (int32_t e = a.eoff[f]; e < a.eoff[f + 1]; ++e) {
+      for (int32_t e = a.eoff[f] + (int32_t)lane; e < a.eoff[f + 1]; e += GP_WAVE) {
         const double4 r = a.edge64[e];
-        const double d2 = seg_d2_64(x, y, r.x, r.y, r.z, r.w);
-        if (d2 < pd) pd = d2;
+        const double dx = r.z - r.x, dy = r.w - r.y;
+        const double wx = x - r.x, wy = y - r.y;
+        const double L2 = dx * dx + dy * dy;
+        const double t = wx * dx + wy * dy;
+        double d2;
+        if (t <= 0.0) {
+          d2 = wx * wx + wy * wy;
+        } else if (t >= L2) {
+          const double ex = x - r.z, ey = y - r.w;
+          d2 = ex * ex + ey * ey;
+        } else {
+          const double c = wx * dy - wy * dx;
+          const double cc = c * c;
+          d2 = cc < (thr * L2) * (1.0 + 0x1p-49) ? cc / L2 : INFINITY;
+        }
+        pd = fmin(pd, d2);
       }
+      pd = wave_min_f64(pd);
       if (pd <= a.D2 && pd < best) { best = pd; bid = f; }
     }
-    a.out_id[j] = bid;
-    a.out_dist[j] = bid >= 0 ? sqrt(best) : INFINITY;
+    if (lane == 0) {
+      a.out_id[j] = bid;
+      a.out_dist[j] = bid >= 0 ? sqrt(best) : INFINITY;
+    }
   }
 }
 
 hipError_t launch_recheck(gp_kind kind, const RefineArgs &a, int num_cu, hipStream_t s) {
-  dim3 grid((unsigned)(num_cu > 0 ? num_cu * 2 : 512)), block(64);
+  dim3 grid((unsigned)(num_cu > 0 ? num_cu * 4 : 1024)), block(256);
   if (kind == GP_PIP) hipLaunchKernelGGL(k_recheck_pip, grid, block, 0, s, a);
   else hipLaunchKernelGGL(k_recheck_p2p, grid, block, 0, s, a);
   return hipGetLastError();

@@ -413,6 +413,16 @@ extern "C" gp_status gp_serve_stats_get(gp_server *srv, gp_serve_stats *out) {
   return GP_OK;
 }
 
+extern "C" gp_status gp_serve_stats_reset(gp_server *srv) {
+  if (!srv) return set_error(GP_E_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->lat_us.clear();
+  srv->completed = srv->failed = srv->points = srv->replays = 0;
+  srv->tests = 0;
+  srv->any = false;
+  return GP_OK;
+}
+
 extern "C" gp_status gp_serve_destroy(gp_server *srv) {
   if (!srv) return set_error(GP_E_INVALID_ARG, "null argument");
   {

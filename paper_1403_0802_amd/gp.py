@@ -111,6 +111,7 @@ _SIGS = {
     "gp_serve_poll": ([_P, c_uint64, POINTER(c_int32)], c_int32),
     "gp_serve_wait": ([_P, c_uint64, c_int64], c_int32),
     "gp_serve_stats_get": ([_P, POINTER(gp_serve_stats)], c_int32),
+    "gp_serve_stats_reset": ([_P], c_int32),
     "gp_serve_destroy": ([_P], c_int32),
 }
 EXPORTED = sorted(_SIGS)
@@ -330,6 +331,11 @@ class Server:
         return s.as_dict()
 
     stats = gp_serve_stats
+
+    def gp_serve_stats_reset(self):
+        check(lib.gp_serve_stats_reset(self.handle))
+
+    reset_stats = gp_serve_stats_reset
 
     def gp_serve_destroy(self):
         h, self.handle = self.handle, None

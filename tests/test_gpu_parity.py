@@ -50,16 +50,17 @@ def run_gpu(gp, grid, px, py, prec, stats=False, tuning=None):
 
 
 def check_p2p(got_id, got_d, want_id, want_d, prec, where=""):
+    """Ids bit-exact in both forms.  Distances: the FP64 form is bitwise equal to the
+    oracle; the mixed form reports FP64 distances of its winners (recomputed over the
+    winning polyline), so it must be bitwise equal as well -- MIXED_TOL is the looser
+    bound the FP32 distances alone would satisfy, kept as a diagnostic."""
     assert np.array_equal(got_id, want_id), f"{where}: {np.sum(got_id != want_id)} ids differ"
     hit = want_id >= 0
     assert np.all(np.isinf(got_d[~hit])), where
-    if prec == "fp64":
-        assert np.array_equal(got_d, want_d), f"{where}: FP64 distances are not bitwise equal"
-    else:
-        err = np.abs(got_d[hit] - want_d[hit])
-        assert err.size == 0 or err.max() <= MIXED_TOL, f"{where}: max err {err.max()}"
-        return float(err.max()) if err.size else 0.0
-    return 0.0
+    err = np.abs(got_d[hit] - want_d[hit])
+    assert err.size == 0 or err.max() <= MIXED_TOL, f"{where}: max err {err.max()}"
+    assert np.array_equal(got_d, want_d), f"{where} {prec}: distances are not bitwise equal"
+    return float(err.max()) if err.size else 0.0
 
 
 # ---------------------------------------------------------------------------- pairing
@@ -406,9 +407,8 @@ def test_c4_scaled_mixed_vs_oracle_sample(gp):
     i64, d64, s64 = run_gpu(gp, grid, px, py, "fp64", stats=True)
     imx, dmx, smx = run_gpu(gp, grid, px, py, "mixed", stats=True)
     assert np.array_equal(i64, imx), np.sum(i64 != imx)
-    hit = i64 >= 0
-    err = np.abs(d64[hit] - dmx[hit])
-    assert err.max() <= MIXED_TOL
+    assert np.array_equal(d64, dmx)
+    err = np.abs(d64[i64 >= 0] - dmx[i64 >= 0])
     idx = np.random.default_rng(1).choice(len(px), 20_000, replace=False)
     og = oracle.build_grid(geom, params)
     wid, wd = oracle.p2p(geom, px[idx], py[idx], 100.0, og)
