@@ -57,6 +57,54 @@ def load_traffic(kernel: str, workload: str):
     return e.get("hbm_bytes_per_launch")
 
 
+COPY_PROBE_BYTES = 1 << 30
+
+
+def _pmc_rows(path):
+    import csv
+    return list(csv.DictReader(open(path)))
+
+
+def write_traffic(fetch_csv: str, write_csv: str):
+    """HBM bytes per launch of the refinement kernels from rocprofv3 --pmc counter files
+    (FETCH_SIZE and WRITE_SIZE, KiB per dispatch), each scaled by what the same counter
+    reads for the plain 1 GiB copy of --copy-probe."""
+    out = {}
+    per = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = [r for r in _pmc_rows(path) if r.get("Counter_Name") == counter]
+        # the probe is the largest copy dispatch (it reads and writes 1 GiB)
+        copy = [float(r["Counter_Value"]) for r in rows if "copybuffer" in r["Kernel_Name"].lower()]
+        copy = [c for c in copy if c > 0.25 * COPY_PROBE_BYTES / 1024]
+        factor = (max(copy) * 1024.0 / COPY_PROBE_BYTES) if copy else None
+        per[counter] = {"copy_factor": factor}
+        for r in rows:
+            name = r["Kernel_Name"]
+            for k in ("k_p2pmix", "k_pipmix", "k_p2p64", "k_pip64"):
+                if f"gp::{k}<" in name:
+                    per[counter].setdefault(k, []).append(float(r["Counter_Value"]))
+    for k in ("k_p2pmix", "k_pipmix", "k_p2p64", "k_pip64"):
+        f = per["FETCH_SIZE"].get(k)
+        w = per["WRITE_SIZE"].get(k)
+        ff, wf = per["FETCH_SIZE"]["copy_factor"], per["WRITE_SIZE"]["copy_factor"]
+        if not f or not w or not ff or not wf:
+            continue
+        fb = float(np.median(f)) * 1024.0 / ff
+        wb = float(np.median(w)) * 1024.0 / wf
+        out[k] = {"kernel_source_sha": kernel_hash(),
+                  "workload": WORKLOAD_NAME,
+                  "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                  "hbm_bytes_per_launch": fb + wb,
+                  "copy_factor_fetch": ff, "copy_factor_write": wf,
+                  "launches": len(f)}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    json.dump(out, open(TRAFFIC_FILE, "w"), indent=1, sort_keys=True)
+    print(json.dumps(out, indent=1))
+
+
+WORKLOAD_NAME = "C3 PIP 50M pts x 5000 polygons + C4 P2P 200M pts x 200000 polylines, mixed"
+
+
 def build_workloads(scale: float):
     from paper_1403_0802_amd import synth
     t0 = time.time()
@@ -172,8 +220,16 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run one plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc counter "
+                         "CSVs of a --copy-probe run, then exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(*args.traffic_from)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -205,7 +261,14 @@ def main():
     id4 = torch.empty(x4.numel(), dtype=torch.int32, device=dev)
     d4 = torch.empty(x4.numel(), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
-    if args.autotune:
+    if args.copy_probe:
+        src = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if not args.no_autotune:
+        # the autotuner times each kernel configuration on a sample of the workload
         n_s = min(x3.numel(), 4_000_000)
         log("[bench] autotune pip", gp.gp_autotune(grid3, prec, x3[:n_s], y3[:n_s], ws3))
         n_s = min(x4.numel(), 8_000_000)
@@ -244,7 +307,7 @@ def main():
     dom = "p2p" if p2p_ref >= pip_ref else "pip"
     dom_kernel = "k_p2pmix" if dom == "p2p" else "k_pipmix"
     achieved = p2p_flops if dom == "p2p" else pip_flops
-    workload = "C3 PIP 50M pts x 5000 polygons + C4 P2P 200M pts x 200000 polylines, mixed"
+    workload = WORKLOAD_NAME
     if args.scale != 1.0:
         workload += f" (points x{args.scale})"
     traffic = load_traffic(dom_kernel, workload)

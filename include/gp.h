@@ -113,6 +113,8 @@ typedef struct gp_tuning {
     int32_t edge_chunk;      /* edges staged in LDS per round: 64..512, multiple of 64 */
     int32_t wg_per_cu;       /* persistent workgroups per compute unit: 1..32 */
     int32_t persistent;      /* 1: persistent work queue; 0: one workgroup per item */
+    int32_t waves_per_item;  /* P2P: 1, 2 or 4 wavefronts share one LDS staging and a work
+                                item holds up to 64*ppl*waves points; PIP: always 1 */
 } gp_tuning;
 
 /* Per-call counters.  Filling them synchronises the stream at the end of the call. */

@@ -64,16 +64,19 @@ struct DevBuf {
 static gp_tuning default_tuning(gp_kind kind, gp_precision prec) {
   gp_tuning t;
   t.points_per_lane = (prec == GP_MIXED && kind == GP_P2P) ? 2 : 1;
-  t.edge_chunk = 256;
-  t.wg_per_cu = 16;
-  t.persistent = 1;
+  t.edge_chunk = prec == GP_MIXED ? 128 : 256;
+  t.wg_per_cu = (prec == GP_MIXED && kind == GP_P2P) ? 32 : 16;
+  t.persistent = (prec == GP_MIXED && kind == GP_PIP) ? 0 : 1;
+  t.waves_per_item = 1;
   return t;
 }
 
-static bool tuning_valid(const gp_tuning &t) {
+static bool tuning_valid(const gp_tuning &t, gp_kind kind) {
+  const int w = t.waves_per_item;
   return (t.points_per_lane == 1 || t.points_per_lane == 2 || t.points_per_lane == 4) &&
          t.edge_chunk >= 64 && t.edge_chunk <= 512 && t.edge_chunk % 64 == 0 &&
-         t.wg_per_cu >= 1 && t.wg_per_cu <= 32 && (t.persistent == 0 || t.persistent == 1);
+         t.wg_per_cu >= 1 && t.wg_per_cu <= 32 && (t.persistent == 0 || t.persistent == 1) &&
+         (w == 1 || (kind == GP_P2P && (w == 2 || w == 4)));
 }
 
 // ------------------------------------------------------------------------- geometry checks
@@ -212,6 +215,33 @@ extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
                                   g->d_edge64, g->d_k32, g->d_eoff, s));
   GP_TRY_HIP_G(launch_mbb(d_rvo.as<int32_t>(), d_fro.as<int32_t>(), d_x.as<double>(),
                           d_y.as<double>(), (int32_t)nf, kind, D, cs, d_mbb.as<double>(), s));
+  {
+    // Bound on |coordinate - cell centre| over every segment of every candidate of a
+    // cell: the largest feature MBB diagonal plus D plus a cell diagonal.  The mixed
+    // P2P kernel scales its frame constants by a power of two below 1/(4 * bound).
+    double diag = 0.0;
+    for (int64_t f = 0; f < nf; ++f) {
+      int64_t v0 = h.rvo[kind == GP_PIP ? h.fro[f] : f];
+      int64_t v1 = h.rvo[kind == GP_PIP ? h.fro[f + 1] : f + 1];
+      double lx = INFINITY, ly = INFINITY, hx = -INFINITY, hy = -INFINITY;
+      for (int64_t v = v0; v < v1; ++v) {
+        lx = std::min(lx, h.x[v]); hx = std::max(hx, h.x[v]);
+        ly = std::min(ly, h.y[v]); hy = std::max(hy, h.y[v]);
+      }
+      if (v1 > v0) diag = std::max(diag, std::hypot(hx - lx, hy - ly));
+    }
+    const double bound = diag + D + 2.0 * cs;
+    int e = (int)std::ceil(std::log2(4.0 * bound));
+    e = std::max(-100, std::min(100, e));
+    g->p2p_scale = (float)std::ldexp(1.0, -e);
+  }
+  if (kind == GP_P2P) {
+    const size_t ns = (size_t)std::max<int64_t>(nedges, 1);
+    GP_TRY_HIP_G(hipMalloc(&g->d_frame64, ns * sizeof(double4)));
+    GP_TRY_HIP_G(hipMalloc(&g->d_frame32, ns * sizeof(float4)));
+    GP_TRY_HIP_G(launch_build_frames(g->d_edge64, (int32_t)nedges, g->p2p_scale, g->d_frame64,
+                                     g->d_frame32, s));
+  }
 
   // extent
   double x0 = params->x0, y0 = params->y0;
@@ -300,6 +330,8 @@ extern "C" void gp_grid_free(gp_grid *g) {
   (void)hipFree(g->d_eoff);
   (void)hipFree(g->d_edge64);
   (void)hipFree(g->d_k32);
+  (void)hipFree(g->d_frame64);
+  (void)hipFree(g->d_frame32);
   (void)hipFree(g->d_cand_off);
   (void)hipFree(g->d_cand_id);
   (void)hipFree(g->d_cell_edges);
@@ -424,7 +456,7 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   if (!ws || ws_bytes < need)
     return set_error(GP_E_INVALID_ARG, "workspace too small: %zu bytes needed", need);
   const gp_tuning t = override_tuning ? *override_tuning : g->tune[prec];
-  if (!tuning_valid(t)) return set_error(GP_E_INVALID_ARG, "invalid tuning");
+  if (!tuning_valid(t, g->kind)) return set_error(GP_E_INVALID_ARG, "invalid tuning");
 
   hipEvent_t ev[5] = {};
   if (stats) {
@@ -447,6 +479,8 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   a.eoff = g->d_eoff;
   a.edge64 = g->d_edge64;
   a.k32 = g->d_k32;
+  a.frame64 = g->d_frame64;
+  a.frame32 = g->d_frame32;
   a.x0 = g->x0;
   a.y0 = g->y0;
   a.cs = g->cs;
@@ -457,6 +491,7 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   a.D2_next = std::nextafter(g->D2, INFINITY);
   a.half_box = half_box(*g);
   a.p2p_margin = (float)std::max(0.01 * g->D, g->cs * 0x1p-10);
+  a.p2p_scale = g->p2p_scale;
   a.skey = skey;
   a.perm = perm;
   a.xy = xy;
@@ -468,10 +503,11 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
 
   GP_TRY_HIP(launch_unpaired(a, n, w.counters + C_NPAIRED, s));
   GP_TRY_HIP(launch_items(w.pt_off, g->d_cand_off, g->d_cell_edges, g->ncells,
-                          64 * t.points_per_lane, w.item_cnt, w.scan_tmp, w.items, w.counters,
-                          w.tests, s));
+                          64 * t.points_per_lane * t.waves_per_item, w.item_cnt, w.scan_tmp,
+                          w.items, w.counters, w.tests, s));
   if (stats) GP_TRY_HIP(hipEventRecord(ev[1], s));
-  const int64_t mi = n / (64 * t.points_per_lane) + std::min<int64_t>(g->ncells, n) + 1;
+  const int64_t mi = n / (64 * t.points_per_lane * t.waves_per_item) +
+                    std::min<int64_t>(g->ncells, n) + 1;
   GP_TRY_HIP(launch_refine(kind, prec, a, t, g->num_cu, mi, s));
   if (stats) GP_TRY_HIP(hipEventRecord(ev[2], s));
   if (prec == GP_MIXED) GP_TRY_HIP(launch_recheck(kind, a, g->num_cu, s));
@@ -557,7 +593,8 @@ extern "C" gp_status gp_set_tuning(gp_grid *g, gp_precision prec, const gp_tunin
   if (v.points_per_lane == 0) v.points_per_lane = d.points_per_lane;
   if (v.edge_chunk == 0) v.edge_chunk = d.edge_chunk;
   if (v.wg_per_cu == 0) v.wg_per_cu = d.wg_per_cu;
-  if (!tuning_valid(v)) return set_error(GP_E_INVALID_ARG, "invalid tuning");
+  if (v.waves_per_item == 0) v.waves_per_item = d.waves_per_item;
+  if (!tuning_valid(v, g->kind)) return set_error(GP_E_INVALID_ARG, "invalid tuning");
   g->tune[prec] = v;
   return GP_OK;
 }
@@ -585,9 +622,14 @@ extern "C" gp_status gp_autotune(gp_grid *g, gp_precision prec, int64_t n, const
   const int ppls[3] = {1, 2, 4}, ecs[3] = {128, 256, 512}, wgs[4] = {8, 12, 16, 32};
   for (int p : ppls)
     for (int e : ecs)
-      for (int wgc : wgs) space.push_back(gp_tuning{p, e, wgc, 1});
+      for (int wgc : wgs) space.push_back(gp_tuning{p, e, wgc, 1, 1});
   for (int p : ppls)
-    for (int e : ecs) space.push_back(gp_tuning{p, e, 16, 0});
+    for (int e : ecs) space.push_back(gp_tuning{p, e, 16, 0, 1});
+  if (g->kind == GP_P2P)
+    for (int wv : {2, 4})
+      for (int p : ppls)
+        for (int e : ecs)
+          for (int wgc : {4, 8, 16}) space.push_back(gp_tuning{p, e, wgc, 1, wv});
   float best_t = INFINITY;
   gp_tuning best_cfg = g->tune[prec];
   for (const gp_tuning &t : space) {

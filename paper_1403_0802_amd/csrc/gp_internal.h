@@ -32,11 +32,14 @@ struct RefineArgs {
   const int32_t *eoff;       // [nf+1] edge (PIP) or segment (P2P) range of a feature
   const double4 *edge64;     // PIP: (lo.x, lo.y, hi.x, hi.y); P2P: (a.x, a.y, b.x, b.y)
   const float *k32;          // PIP: fl32(w/h), 0 for horizontal edges
+  const double4 *frame64;    // P2P: (u.x, u.y, -m.u, -m.v) of each segment, absolute m
+  const float4 *frame32;     // P2P: (u.x*scale, u.y*scale, |d|/2*scale, |d|)
   double x0, y0, cs;
   int32_t nx, ncells;
   double D, D2, D2_next;     // P2P: D, fl(D*D), the smallest double above fl(D*D)
   float half_box;            // bound on |rebased point coordinate| inside its cell
   float p2p_margin;          // P2P: T, the "near the cell" margin (distance units)
+  float p2p_scale;           // P2P mixed: power of two; |rebased coordinate| * scale < 1/4
   // points, sorted by cell
   const uint32_t *skey;      // sorted cell ids
   const uint32_t *perm;      // sorted position -> caller index
@@ -60,9 +63,12 @@ struct Grid {
   int32_t *d_eoff;
   double4 *d_edge64;
   float *d_k32;
+  double4 *d_frame64;
+  float4 *d_frame32;
   int32_t *d_cand_off;
   int32_t *d_cand_id;
   int64_t *d_cell_edges;  // [ncells] sum of nedges over the cell's candidates
+  float p2p_scale;        // see RefineArgs
   gp_tuning tune[2];
   int num_cu;
 };
@@ -106,6 +112,8 @@ hipError_t launch_build_edges(const int32_t *ring_vert_off, const int32_t *featu
                               const double *x, const double *y, int32_t nf, int32_t nrings,
                               int32_t nverts, gp_kind kind, double4 *edge64, float *k32,
                               int32_t *eoff, hipStream_t s);
+hipError_t launch_build_frames(const double4 *seg64, int32_t nseg, float scale,
+                               double4 *frame64, float4 *frame32, hipStream_t s);
 hipError_t launch_mbb(const int32_t *ring_vert_off, const int32_t *feature_ring_off,
                       const double *x, const double *y, int32_t nf, gp_kind kind, double D,
                       double cs, double *mbb, hipStream_t s);

@@ -350,6 +350,31 @@ hipError_t launch_build_edges(const int32_t *rvo, const int32_t *fro, const doub
   return hipGetLastError();
 }
 
+// P2P segment frames: u = d/|d| (u = (1, 0) for a zero-length segment), the absolute
+// midpoint projections -m.u and -m.v with v = (-u.y, u.x), and the scaled FP32 constants
+// the mixed kernel stages unchanged for every cell.
+__global__ void k_build_frames(const double4 *seg, int32_t nseg, float scale, double4 *f64,
+                               float4 *f32) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += gridDim.x * blockDim.x) {
+    const double4 r = seg[i];
+    const double dx = r.z - r.x, dy = r.w - r.y;
+    const double L = sqrt(dx * dx + dy * dy);
+    const double ux = L > 0.0 ? dx / L : 1.0, uy = L > 0.0 ? dy / L : 0.0;
+    const double mx = r.x + 0.5 * dx, my = r.y + 0.5 * dy;
+    f64[i] = make_double4(ux, uy, -(mx * ux + my * uy), mx * uy - my * ux);
+    const double sc = (double)scale;
+    f32[i] = make_float4((float)(ux * sc), (float)(uy * sc), (float)(0.5 * L * sc), (float)L);
+  }
+}
+
+hipError_t launch_build_frames(const double4 *seg64, int32_t nseg, float scale,
+                               double4 *frame64, float4 *frame32, hipStream_t s) {
+  if (nseg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_build_frames, dim3(grid_for(nseg, 256, 8192)), dim3(256), 0, s, seg64, nseg,
+                     scale, frame64, frame32);
+  return hipGetLastError();
+}
+
 // Feature MBB over all of its vertices; P2P expands by D; both pad by cs*2^-20.
 __global__ void k_mbb(const int32_t *rvo, const int32_t *fro, const double *x, const double *y,
                       int32_t nf, int kind, double D, double cs, double *mbb) {
@@ -930,14 +955,31 @@ struct alignas(16) SegRec64 {
 };
 
 // ------------------------------------------------------------------------- P2P, FP64
+// P2P work items may span W wavefronts (W*64*PPL points) that share one LDS staging of
+// the segments; every wave owns its own points and results.
 
-template <int PPL>
+template <int PPL, int W>
+__device__ __forceinline__ void load_points64w(const RefineArgs &a, const Item it,
+                                               double (&px)[PPL], double (&py)[PPL]) {
+  const int base = (int)(threadIdx.x / GP_WAVE) * GP_WAVE * PPL + (int)lane_id();
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    const int idx = base + GP_WAVE * j;
+    const double2 p = idx < it.npts ? a.xy[it.pt_lo + idx] : make_double2(0.0, 0.0);
+    px[j] = p.x;
+    py[j] = p.y;
+  }
+}
+
+template <int PPL, int W>
 __device__ void p2p64_item(const RefineArgs &a, const Item it, SegRec64 *lds, int2 *tab) {
-  const uint32_t lane = lane_id();
+  const int tid = (int)threadIdx.x;
+  const int wbase = (int)(threadIdx.x / GP_WAVE) * GP_WAVE * PPL;
+  const bool wave_live = wbase < it.npts;
   const int EC = a.edge_chunk;
   double px[PPL], py[PPL], best[PPL];
   int32_t bid[PPL];
-  load_points64<PPL>(a, it, px, py);
+  load_points64w<PPL, W>(a, it, px, py);
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
     best[j] = a.D2_next;  // accept d2 <= fl(D*D); later only strictly smaller
@@ -953,7 +995,7 @@ __device__ void p2p64_item(const RefineArgs &a, const Item it, SegRec64 *lds, in
       const int32_t f = a.cand_id[k];
       const int32_t s0 = a.eoff[f] + soff, s1 = a.eoff[f + 1];
       const int take = (s1 - s0) < (EC - filled) ? (s1 - s0) : (EC - filled);
-      for (int t = lane; t < take; t += GP_WAVE) {
+      for (int t = tid; t < take; t += GP_WAVE * W) {
         const double4 r = a.edge64[s0 + t];
         SegRec64 q;
         q.ax = r.x; q.ay = r.y; q.bx = r.z; q.by = r.w;
@@ -965,12 +1007,13 @@ __device__ void p2p64_item(const RefineArgs &a, const Item it, SegRec64 *lds, in
       }
       filled += take;
       const bool cont = s0 + take < s1;
-      if (lane == 0) tab[ntab] = make_int2(f, filled | (cont ? (int)0x80000000 : 0));
+      if (tid == 0) tab[ntab] = make_int2(f, filled | (cont ? (int)0x80000000 : 0));
       ++ntab;
       if (cont) soff += take;
       else { ++k; soff = 0; }
     }
     __syncthreads();
+    if (!wave_live) continue;
     int start = 0;
     for (int q = 0; q < ntab; ++q) {
       const int2 te = tab[q];
@@ -1004,7 +1047,7 @@ __device__ void p2p64_item(const RefineArgs &a, const Item it, SegRec64 *lds, in
   }
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
-    const int idx = (int)lane + GP_WAVE * j;
+    const int idx = wbase + (int)lane_id() + GP_WAVE * j;
     if (idx < it.npts) {
       const uint32_t o = a.perm[it.pt_lo + idx];
       a.out_id[o] = bid[j];
@@ -1014,49 +1057,72 @@ __device__ void p2p64_item(const RefineArgs &a, const Item it, SegRec64 *lds, in
 }
 
 // ------------------------------------------------------------------------- P2P, mixed
-// FP32 on cell-rebased coordinates.  Per segment the LDS holds a, d = b - a, d/|d|^2 and
-// -(a.d)/|d|^2, so the clamped projection parameter is two FMAs (the clamp is free) and
-// a point-segment test is 9 VALU operations; the minimum is taken on the float bits as
-// unsigned integers (valid for d^2 >= 0), two segments per v_min3.
+// FP32 on cell-rebased coordinates, in each segment's own frame.  With u = d/|d|,
+// v = (-u.y, u.x), m the segment midpoint and h = |d|/2, the point-segment distance is
+// sqrt(e^2 + r^2) with s = (p - m).u, r = (p - m).v and e = max(0, |s| - h).  The LDS
+// holds u, v, -m.u, -m.v and h, all multiplied by a per-grid power of two `scale` that
+// keeps |s| * scale below 1/2; then s and r are two FMAs each, e is one subtract with
+// the |.| and clamp-to-[0,1] modifiers (the upper clamp never binds), and e^2 + r^2 is
+// two more -- 7 VALU operations per test, plus half a v_min3_u32 (minimum on the float
+// bits as unsigned integers, valid for d^2 >= 0).  Scaling by a power of two is exact.
+// The frame (u, h, and the absolute -m.u, -m.v) is precomputed per segment when the
+// grid is built; staging for a cell c only adds c.u and c.v in FP64.
 //
-// Per point the wave tracks the best and second-best polyline (distinct ids).  With E
-// the largest error bound e_s = 48*2^-24*(B*sqrt2 + M_s) over segments near the cell
-// (M_s: largest rebased |coordinate| of the segment; 48 is four times the constant of
-// the rounding analysis), the id is decided in FP32 only when the winner is inside
-// D - E and beats the runner-up by more than 2E, or when nothing is within D + E; all
-// other points go to the FP64 recheck.  The reported distance of an FP32-decided hit is
-// recomputed in FP64 over the winner's segments, so it equals the FP64 result bitwise.
+// Per point the wave tracks the three best polylines (distinct ids; ids of the first
+// two).  E is the largest error bound e_s = 48*2^-24*(B*sqrt2 + |m - c| + |d|) over the
+// segments near the cell (48 is four times the constant of the rounding analysis).
+//  * best > D + E: nothing within D (FP64 agrees);
+//  * second > best + 2E: only the best polyline can be the answer; its exact FP64
+//    distance decides (within D or not);
+//  * third > best + 2E: only the best two can be the answer; their exact FP64
+//    distances decide (smaller distance, then smaller id);
+//  * otherwise (a three-way near-tie): the point goes to the FP64 recheck queue.
+// Reported distances are therefore always FP64 values.
 
-__device__ __forceinline__ uint32_t seg_d2_bits(float px, float py, const float4 s0,
-                                                const float4 s1) {
-  const float tt = __builtin_amdgcn_fmed3f(fmaf(px, s1.x, fmaf(py, s1.y, s1.z)), 0.0f, 1.0f);
-  const float wx = px - s0.x, wy = py - s0.y;
-  const float qx = fmaf(-tt, s0.z, wx), qy = fmaf(-tt, s0.w, wy);
-  return __float_as_uint(fmaf(qx, qx, qy * qy));
+__device__ __forceinline__ uint32_t seg_d2_bits(float px, float py, const float4 U,
+                                                const float4 V) {
+  const float s = fmaf(px, U.x, fmaf(py, U.y, U.z));
+  const float r = fmaf(px, V.x, fmaf(py, V.y, V.z));
+  const float e = __builtin_amdgcn_fmed3f(fabsf(s) - U.w, 0.0f, 1.0f);
+  return __float_as_uint(fmaf(e, e, r * r));
 }
 
-template <int PPL>
-__device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsS0, float4 *ldsS1,
-                            int2 *tab) {
+template <int PPL, int W>
+__device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, float4 *ldsV,
+                            int2 *tab, float *red) {
+  const int tid = (int)threadIdx.x;
   const uint32_t lane = lane_id();
+  const int wave = (int)(threadIdx.x / GP_WAVE);
+  const int wbase = wave * GP_WAVE * PPL;
+  const bool wave_live = wbase < it.npts;
   const int EC = a.edge_chunk;
   const double cx = cell_cx(a, (uint32_t)it.cell), cy = cell_cy(a, (uint32_t)it.cell);
   const float hb = a.half_box;
   const float T = a.p2p_margin;
-  const float near_lim = (float)a.D + T;
+  const float near_lim = (float)a.D + T + hb * 1.4143f;
+  const double sc = (double)a.p2p_scale;
+  const double inv_sc = 1.0 / sc;
   float px[PPL], py[PPL];
-  uint32_t b1[PPL], b2[PPL], pm[PPL];
-  int32_t f1[PPL];
-  load_points32<PPL>(a, it, cx, cy, px, py);
+  uint32_t b1[PPL], b2[PPL], b3[PPL], pm[PPL];
+  int32_t f1[PPL], f2[PPL];
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    const int idx = wbase + (int)lane + GP_WAVE * j;
+    const double2 p = idx < it.npts ? a.xy[it.pt_lo + idx] : make_double2(cx, cy);
+    px[j] = (float)(p.x - cx);
+    py[j] = (float)(p.y - cy);
+  }
   const uint32_t INFB = 0x7f800000u;
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
     b1[j] = INFB;
     b2[j] = INFB;
+    b3[j] = INFB;
     pm[j] = INFB;
     f1[j] = -1;
+    f2[j] = -1;
   }
-  float emax = 0.0f;  // per-lane partial of E over the segments this lane staged
+  float emax = 0.0f;  // per-thread partial of E over the segments this thread staged
   int32_t k = a.cand_off[it.cell];
   const int32_t k1 = a.cand_off[it.cell + 1];
   int32_t soff = 0;
@@ -1067,33 +1133,30 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsS0, f
       const int32_t f = a.cand_id[k];
       const int32_t s0 = a.eoff[f] + soff, s1 = a.eoff[f + 1];
       const int take = (s1 - s0) < (EC - filled) ? (s1 - s0) : (EC - filled);
-      for (int t = lane; t < take; t += GP_WAVE) {
-        const double4 r = a.edge64[s0 + t];
-        const double ax = r.x - cx, ay = r.y - cy;
-        const double ddx = r.z - r.x, ddy = r.w - r.y;
-        const double L2 = ddx * ddx + ddy * ddy;
-        const double inv = L2 > 0.0 ? 1.0 / L2 : 0.0;
-        ldsS0[filled + t] = make_float4((float)ax, (float)ay, (float)ddx, (float)ddy);
-        ldsS1[filled + t] = make_float4((float)(ddx * inv), (float)(ddy * inv),
-                                        (float)(-(ax * ddx + ay * ddy) * inv), 0.0f);
-        const float fax = (float)ax, fay = (float)ay;
-        const float fbx = (float)(r.z - cx), fby = (float)(r.w - cy);
-        const float M = fmaxf(fmaxf(fabsf(fax), fabsf(fay)), fmaxf(fabsf(fbx), fabsf(fby)));
-        const float es = 48.0f * 0x1p-24f * (hb * 1.4143f + M);
-        const float gx = fmaxf(0.0f, fmaxf(fminf(fax, fbx) - hb, -hb - fmaxf(fax, fbx)));
-        const float gy = fmaxf(0.0f, fmaxf(fminf(fay, fby) - hb, -hb - fmaxf(fay, fby)));
-        const bool nearc = (gx <= near_lim && gy <= near_lim &&
-                            sqrtf(gx * gx + gy * gy) <= near_lim) || !(es <= 0.5f * T);
+      for (int t = tid; t < take; t += GP_WAVE * W) {
+        const double4 F = a.frame64[s0 + t];
+        const float4 G = a.frame32[s0 + t];
+        // centre's frame coordinates: s_c = -(m - c).u, r_c = -(m - c).v
+        const double sC = F.z + (cx * F.x + cy * F.y);
+        const double rC = F.w + (cy * F.x - cx * F.y);
+        ldsU[filled + t] = make_float4(G.x, G.y, (float)(sC * sc), G.z);
+        ldsV[filled + t] = make_float4(-G.y, G.x, (float)(rC * sc), 0.0f);
+        // error bound and "near the cell" test, in distance units
+        const float fs = fabsf((float)sC), fr = fabsf((float)rC);
+        const float es = 48.0f * 0x1p-24f * (hb * 1.4143f + sqrtf(fs * fs + fr * fr) + G.w);
+        const float ex = fmaxf(0.0f, fs - 0.5f * G.w);
+        const bool nearc = !(sqrtf(ex * ex + fr * fr) > near_lim) || !(es <= 0.5f * T);
         if (nearc) emax = fmaxf(emax, es);
       }
       filled += take;
       const bool cont = s0 + take < s1;
-      if (lane == 0) tab[ntab] = make_int2(f, filled | (cont ? (int)0x80000000 : 0));
+      if (tid == 0) tab[ntab] = make_int2(f, filled | (cont ? (int)0x80000000 : 0));
       ++ntab;
       if (cont) soff += take;
       else { ++k; soff = 0; }
     }
     __syncthreads();
+    if (!wave_live) continue;
     int start = 0;
     for (int q = 0; q < ntab; ++q) {
       const int2 te = tab[q];
@@ -1101,57 +1164,77 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsS0, f
       const int end = te.y & 0x7fffffff;
       int t = start;
       for (; t + 2 <= end; t += 2) {
-        const float4 s00 = ldsS0[t], s01 = ldsS1[t], s10 = ldsS0[t + 1], s11 = ldsS1[t + 1];
+        const float4 u0 = ldsU[t], v0 = ldsV[t], u1 = ldsU[t + 1], v1 = ldsV[t + 1];
 #pragma unroll
         for (int j = 0; j < PPL; ++j)
-          pm[j] = min(pm[j], min(seg_d2_bits(px[j], py[j], s00, s01),
-                                 seg_d2_bits(px[j], py[j], s10, s11)));
+          pm[j] = min(pm[j], min(seg_d2_bits(px[j], py[j], u0, v0),
+                                 seg_d2_bits(px[j], py[j], u1, v1)));
       }
       if (t < end) {
-        const float4 s00 = ldsS0[t], s01 = ldsS1[t];
+        const float4 u0 = ldsU[t], v0 = ldsV[t];
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) pm[j] = min(pm[j], seg_d2_bits(px[j], py[j], s00, s01));
+        for (int j = 0; j < PPL; ++j) pm[j] = min(pm[j], seg_d2_bits(px[j], py[j], u0, v0));
       }
       if (!(te.y & (int)0x80000000)) {
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-          if (pm[j] < b1[j]) { b2[j] = b1[j]; b1[j] = pm[j]; f1[j] = f; }
-          else if (pm[j] < b2[j]) b2[j] = pm[j];
+          if (pm[j] < b1[j]) {
+            b3[j] = b2[j]; b2[j] = b1[j]; f2[j] = f1[j]; b1[j] = pm[j]; f1[j] = f;
+          } else if (pm[j] < b2[j]) {
+            b3[j] = b2[j]; b2[j] = pm[j]; f2[j] = f;
+          } else if (pm[j] < b3[j]) {
+            b3[j] = pm[j];
+          }
           pm[j] = INFB;
         }
       }
       start = end;
     }
   }
+  // E = maximum over the whole workgroup's staged segments
   for (int off = 32; off > 0; off >>= 1) emax = fmaxf(emax, __shfl_xor(emax, off, GP_WAVE));
+  if (W > 1) {
+    if (lane == 0) red[wave] = emax;
+    __syncthreads();
+    for (int w = 0; w < W; ++w) emax = fmaxf(emax, red[w]);
+    __syncthreads();
+  }
+  if (!wave_live) return;
   const double E = (double)emax;
   const double D = a.D;
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
-    const int idx = (int)lane + GP_WAVE * j;
+    const int idx = wbase + (int)lane + GP_WAVE * j;
     const bool v = idx < it.npts;
-    const double d1 = (double)sqrtf(__uint_as_float(b1[j]));
-    const double d2 = (double)sqrtf(__uint_as_float(b2[j]));
-    const bool hit = (d1 < D - E) && (d2 - d1 > 2.0 * E);
+    const double d1 = (double)sqrtf(__uint_as_float(b1[j])) * inv_sc;
+    const double d2 = (double)sqrtf(__uint_as_float(b2[j])) * inv_sc;
+    const double d3 = (double)sqrtf(__uint_as_float(b3[j])) * inv_sc;
     const bool miss = d1 > D + E;
-    const bool flag = !(hit || miss);
-    if (v && hit) {
-      // exact FP64 distance to the winning polyline
+    // candidates for the answer: f1 alone, or f1 and f2 (every other polyline is
+    // provably farther than both); their exact FP64 distances decide
+    const int ncand = miss ? 0 : (d2 - d1 > 2.0 * E) ? 1 : (d3 - d1 > 2.0 * E) ? 2 : 3;
+    if (v && (ncand == 1 || ncand == 2)) {
       const double2 p = a.xy[it.pt_lo + idx];
-      double pd = INFINITY;
-      for (int32_t e = a.eoff[f1[j]]; e < a.eoff[f1[j] + 1]; ++e) {
-        const double4 r = a.edge64[e];
-        pd = fmin(pd, seg_d2_64(p.x, p.y, r.x, r.y, r.z, r.w));
+      int32_t bid = -1;
+      double best = INFINITY;
+      for (int c = 0; c < ncand; ++c) {
+        const int32_t f = c == 0 ? f1[j] : f2[j];
+        double pd = INFINITY;
+        for (int32_t e = a.eoff[f]; e < a.eoff[f + 1]; ++e) {
+          const double4 r = a.edge64[e];
+          pd = fmin(pd, seg_d2_64(p.x, p.y, r.x, r.y, r.z, r.w));
+        }
+        if (pd <= a.D2 && (pd < best || (pd == best && f < bid))) { best = pd; bid = f; }
       }
       const uint32_t o = a.perm[it.pt_lo + idx];
-      a.out_id[o] = f1[j];
-      a.out_dist[o] = sqrt(pd);
+      a.out_id[o] = bid;
+      a.out_dist[o] = bid >= 0 ? sqrt(best) : INFINITY;
     } else if (v && miss) {
       const uint32_t o = a.perm[it.pt_lo + idx];
       a.out_id[o] = -1;
       a.out_dist[o] = INFINITY;
     }
-    push_recheck(a, v && flag, (uint32_t)(it.pt_lo + idx));
+    push_recheck(a, v && ncand == 3, (uint32_t)(it.pt_lo + idx));
   }
 }
 
@@ -1185,32 +1268,43 @@ __global__ __launch_bounds__(64) void k_pipmix(RefineArgs a, int persistent) {
   }
 }
 
-template <int PPL>
-__global__ __launch_bounds__(64) void k_p2p64(RefineArgs a, int persistent) {
+// Work-queue pop for a workgroup of several waves (broadcast through LDS).
+__device__ __forceinline__ uint32_t next_item_wg(const RefineArgs &a, uint32_t *slot) {
+  __syncthreads();
+  if (threadIdx.x == 0) *slot = atomicAdd(a.item_counter, 1u);
+  __syncthreads();
+  return *slot;
+}
+
+template <int PPL, int W>
+__global__ __launch_bounds__(64 * W) void k_p2p64(RefineArgs a, int persistent) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t s_item;
   SegRec64 *lds = (SegRec64 *)smem;
   int2 *tab = (int2 *)(lds + a.edge_chunk);
   const uint32_t n_items = *a.n_items;
-  uint32_t it = persistent ? next_item(a) : blockIdx.x;
+  uint32_t it = persistent ? (W == 1 ? next_item(a) : next_item_wg(a, &s_item)) : blockIdx.x;
   while (it < n_items) {
-    p2p64_item<PPL>(a, a.items[it], lds, tab);
+    p2p64_item<PPL, W>(a, a.items[it], lds, tab);
     if (!persistent) break;
-    it = next_item(a);
+    it = W == 1 ? next_item(a) : next_item_wg(a, &s_item);
   }
 }
 
-template <int PPL>
-__global__ __launch_bounds__(64) void k_p2pmix(RefineArgs a, int persistent) {
+template <int PPL, int W>
+__global__ __launch_bounds__(64 * W) void k_p2pmix(RefineArgs a, int persistent) {
   extern __shared__ __align__(16) unsigned char smem[];
-  float4 *S0 = (float4 *)smem;
-  float4 *S1 = S0 + a.edge_chunk;
-  int2 *tab = (int2 *)(S1 + a.edge_chunk);
+  __shared__ uint32_t s_item;
+  __shared__ float red[4];
+  float4 *U = (float4 *)smem;
+  float4 *V = U + a.edge_chunk;
+  int2 *tab = (int2 *)(V + a.edge_chunk);
   const uint32_t n_items = *a.n_items;
-  uint32_t it = persistent ? next_item(a) : blockIdx.x;
+  uint32_t it = persistent ? (W == 1 ? next_item(a) : next_item_wg(a, &s_item)) : blockIdx.x;
   while (it < n_items) {
-    p2pmix_item<PPL>(a, a.items[it], S0, S1, tab);
+    p2pmix_item<PPL, W>(a, a.items[it], U, V, tab, red);
     if (!persistent) break;
-    it = next_item(a);
+    it = W == 1 ? next_item(a) : next_item_wg(a, &s_item);
   }
 }
 
@@ -1228,6 +1322,23 @@ static size_t refine_lds_bytes(gp_kind kind, gp_precision prec, int ec) {
     else hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__);                               \
   } while (0)
 
+#define GP_DISPATCH_W(KERNEL, PPLV, WV, ...)                                       \
+  do {                                                                             \
+    if ((WV) == 1) {                                                               \
+      if ((PPLV) == 1) hipLaunchKernelGGL((KERNEL<1, 1>), __VA_ARGS__);              \
+      else if ((PPLV) == 2) hipLaunchKernelGGL((KERNEL<2, 1>), __VA_ARGS__);         \
+      else hipLaunchKernelGGL((KERNEL<4, 1>), __VA_ARGS__);                          \
+    } else if ((WV) == 2) {                                                        \
+      if ((PPLV) == 1) hipLaunchKernelGGL((KERNEL<1, 2>), __VA_ARGS__);              \
+      else if ((PPLV) == 2) hipLaunchKernelGGL((KERNEL<2, 2>), __VA_ARGS__);         \
+      else hipLaunchKernelGGL((KERNEL<4, 2>), __VA_ARGS__);                          \
+    } else {                                                                       \
+      if ((PPLV) == 1) hipLaunchKernelGGL((KERNEL<1, 4>), __VA_ARGS__);              \
+      else if ((PPLV) == 2) hipLaunchKernelGGL((KERNEL<2, 4>), __VA_ARGS__);         \
+      else hipLaunchKernelGGL((KERNEL<4, 4>), __VA_ARGS__);                          \
+    }                                                                              \
+  } while (0)
+
 hipError_t launch_refine(gp_kind kind, gp_precision prec, const RefineArgs &a,
                          const gp_tuning &t, int num_cu, int64_t max_items, hipStream_t s) {
   const int ppl = t.points_per_lane;
@@ -1241,14 +1352,16 @@ hipError_t launch_refine(gp_kind kind, gp_precision prec, const RefineArgs &a,
     grid = (unsigned)(max_items < 1 ? 1 : max_items);
   }
   const int pers = t.persistent ? 1 : 0;
+  const int W = kind == GP_P2P ? t.waves_per_item : 1;
+  const dim3 blk(64 * W);
   if (kind == GP_PIP && prec == GP_FP64)
-    GP_DISPATCH(k_pip64, ppl, dim3(grid), dim3(64), lds, s, a, pers);
+    GP_DISPATCH(k_pip64, ppl, dim3(grid), blk, lds, s, a, pers);
   else if (kind == GP_PIP)
-    GP_DISPATCH(k_pipmix, ppl, dim3(grid), dim3(64), lds, s, a, pers);
+    GP_DISPATCH(k_pipmix, ppl, dim3(grid), blk, lds, s, a, pers);
   else if (prec == GP_FP64)
-    GP_DISPATCH(k_p2p64, ppl, dim3(grid), dim3(64), lds, s, a, pers);
+    GP_DISPATCH_W(k_p2p64, ppl, W, dim3(grid), blk, lds, s, a, pers);
   else
-    GP_DISPATCH(k_p2pmix, ppl, dim3(grid), dim3(64), lds, s, a, pers);
+    GP_DISPATCH_W(k_p2pmix, ppl, W, dim3(grid), blk, lds, s, a, pers);
   return hipGetLastError();
 }
 

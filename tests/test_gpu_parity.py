@@ -149,6 +149,11 @@ def test_p2p_c2(gp, c2, prec):
 
 TUNINGS = [dict(points_per_lane=p, edge_chunk=e, wg_per_cu=wg, persistent=pe)
            for p in (1, 2, 4) for e in (64, 256, 512) for wg, pe in ((8, 1), (2, 1), (8, 0))]
+# P2P work items may also span 2 or 4 wavefronts sharing one LDS staging
+TUNINGS_P2P = TUNINGS + [dict(points_per_lane=p, edge_chunk=e, wg_per_cu=wg, persistent=pe,
+                              waves_per_item=wv)
+                         for wv in (2, 4) for p in (1, 4) for e in (64, 512)
+                         for wg, pe in ((4, 1), (8, 0))]
 
 
 @pytest.mark.parametrize("kind", ["pip", "p2p"])
@@ -164,7 +169,7 @@ def test_results_invariant_under_tuning(gp, kind):
     grid = gp.gp_build_grid(kind, w.geom, w.params)
     for prec in ("fp64", "mixed"):
         ref = None
-        for t in TUNINGS:
+        for t in (TUNINGS if kind == "pip" else TUNINGS_P2P):
             r = run_gpu(gp, grid, w.px, w.py, prec, tuning=t)
             if kind == "pip":
                 assert np.array_equal(r, want), (prec, t)

@@ -1,0 +1,143 @@
+"""Serving (continuous batching over resident grids): every request's result is the same
+alone and in a concurrent mix; admission, chunking and error paths behave."""
+import numpy as np
+import pytest
+
+from paper_1403_0802_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_1403_0802_amd import gp
+    geom3, _ = synth.config3_geometry(n_polygons=800, median_v=120, max_v=5000, seed_salt=1)
+    p3 = synth.GridParams(cell_size=1 / 256, nx=256, ny=256)
+    geom4 = synth.config4_geometry(n_lines=20_000, seed_salt=1)
+    p4 = synth.GridParams(cell_size=100.0, radius_D=100.0, nx=400, ny=400)
+    g3 = gp.gp_build_grid("pip", geom3, p3)
+    g4 = gp.gp_build_grid("p2p", geom4, p4)
+    rng = np.random.default_rng(11)
+    sizes = np.exp(rng.uniform(np.log(1000), np.log(300_000), 24)).astype(int)
+    sizes[3] = 70_000  # larger than the small slots below: processed in chunks
+    reqs = []
+    for i, n in enumerate(sizes):
+        kind = "pip" if i % 2 == 0 else "p2p"
+        x, y = synth.request_points(kind, int(n), 1000 + i)
+        reqs.append((kind, torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()))
+    # results of each request alone, through the direct entry points
+    alone = []
+    for kind, x, y in reqs:
+        r = gp.run(g3 if kind == "pip" else g4, x, y, "mixed")
+        alone.append((r.clone(), None) if kind == "pip" else (r[0].clone(), r[1].clone()))
+    torch.cuda.synchronize()
+    return gp, g3, g4, reqs, alone
+
+
+def outputs_for(reqs, device="cuda", pin=False):
+    outs = []
+    for kind, x, _ in reqs:
+        n = x.numel()
+        oid = torch.full((n,), -7, dtype=torch.int32, device=device, pin_memory=pin)
+        od = (torch.full((n,), -7.0, dtype=torch.float64, device=device, pin_memory=pin)
+              if kind == "p2p" else None)
+        outs.append((oid, od))
+    return outs
+
+
+def check_same(alone, outs):
+    for i, ((aid, ad), (oid, od)) in enumerate(zip(alone, outs)):
+        assert torch.equal(aid.cpu(), oid.cpu()), f"request {i}: ids differ from the alone run"
+        if ad is not None:
+            assert torch.equal(ad.cpu(), od.cpu()), f"request {i}: distances differ"
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_mix_equals_alone(setup, graphs):
+    gp, g3, g4, reqs, alone = setup
+    print("serving mix, graphs =", graphs, flush=True)
+    srv = gp.Server(g3, g4, n_slots=4, slot_points=65536, mem_budget=4 << 30,
+                    precision="mixed", inputs_on_device=True, use_graphs=graphs)
+    outs = outputs_for(reqs)
+    for rep in range(2):  # second pass replays the captured graphs
+        tickets = [srv.submit(k, x, y, o[0], o[1]) for (k, x, y), o in zip(reqs, outs)]
+        for t in tickets:
+            srv.wait(t)
+        torch.cuda.synchronize()
+        check_same(alone, outs)
+        for o in outs:
+            o[0].fill_(-7)
+            if o[1] is not None:
+                o[1].fill_(-7.0)
+    st = srv.stats()
+    assert st["completed"] == 2 * len(reqs) and st["failed"] == 0
+    assert st["p50_us"] > 0 and st["p99_us"] >= st["p50_us"]
+    if graphs:
+        assert st["graph_replays"] > 0
+    srv.close()
+
+
+def test_host_inputs_and_tight_budget(setup):
+    gp, g3, g4, reqs, alone = setup
+    print("serving host inputs, one slot", flush=True)
+    per_slot = max(gp.gp_workspace_bytes(g3, 16384, "mixed"),
+                   gp.gp_workspace_bytes(g4, 16384, "mixed")) + 16384 * 28 + 4096
+    srv = gp.Server(g3, g4, n_slots=8, slot_points=16384, mem_budget=per_slot + 1,
+                    precision="mixed", inputs_on_device=False, use_graphs=True)
+    hreqs = [(k, x.cpu().pin_memory(), y.cpu().pin_memory()) for k, x, y in reqs[:10]]
+    outs = outputs_for(hreqs, device="cpu", pin=True)
+    tickets = [srv.submit(k, x, y, o[0], o[1]) for (k, x, y), o in zip(hreqs, outs)]
+    for t in tickets:
+        srv.wait(t)
+    check_same(alone[:10], outs)
+    srv.close()
+
+
+def test_errors(setup):
+    gp, g3, g4, reqs, _ = setup
+    with pytest.raises(gp.GPError) as e:
+        gp.Server(g3, g4, n_slots=2, slot_points=1 << 20, mem_budget=1 << 20)
+    assert e.value.status == gp.GP_E_OOM
+    srv = gp.Server(g3, None, n_slots=1, slot_points=4096, mem_budget=1 << 30, max_queue=1)
+    k, x, y = reqs[1]  # a P2P request against a PIP-only server
+    with pytest.raises(gp.GPError) as e:
+        srv.submit("p2p", x, y, torch.empty(x.numel(), dtype=torch.int32, device="cuda"),
+                   torch.empty(x.numel(), dtype=torch.float64, device="cuda"))
+    assert e.value.status == gp.GP_E_INVALID_ARG
+    with pytest.raises(gp.GPError) as e:
+        srv.wait(12345)
+    assert e.value.status == gp.GP_E_NOT_FOUND
+    # an empty request completes at once
+    t = srv.submit("pip", torch.empty(0, dtype=torch.float64, device="cuda"),
+                   torch.empty(0, dtype=torch.float64, device="cuda"),
+                   torch.empty(0, dtype=torch.int32, device="cuda"))
+    assert srv.poll(t)
+    # a bounded queue refuses work while the only slot is busy
+    k, x, y = reqs[0]
+    busy, accepted = 0, []
+    for _ in range(20):
+        o = torch.empty(x.numel(), dtype=torch.int32, device="cuda")
+        try:
+            accepted.append((srv.submit("pip", x, y, o), o))
+        except gp.GPError as err:
+            assert err.status == gp.GP_E_BUSY
+            busy += 1
+    assert busy > 0
+    for t, o in accepted:
+        srv.wait(t)
+    srv.close()
+    assert gp.lib.gp_serve_destroy(None) == gp.GP_E_INVALID_ARG
+
+
+def test_autotune_keeps_results(setup):
+    gp, g3, g4, reqs, alone = setup
+    kind, x, y = reqs[0]
+    ws = gp.new_workspace(g3, x.numel(), "mixed")
+    best, ms = gp.gp_autotune(g3, "mixed", x, y, ws)
+    assert best["points_per_lane"] in (1, 2, 4) and ms > 0
+    assert gp.gp_get_tuning(g3, "mixed") == best
+    r = gp.run(g3, x, y, "mixed")
+    assert torch.equal(r.cpu(), alone[0][0].cpu())
