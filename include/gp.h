@@ -4,7 +4,7 @@
  * The library computes the two refinement operations of Zhang & You, "Large-Scale
  * Geospatial Processing on Multi-Core and Many-Core Processors" (arXiv 1403.0802):
  *
- *   PIP  (Sec. III.C, Fig. 3): for each point, the polygon it falls within, by the
+ *   PIP  (Sec. III.C, Fig. 3): for each point, the polygon that contains it, by the
  *        even-odd ray-crossing rule over every ring (outer ring and holes).
  *   P2P  (Sec. III.B, Fig. 2): for each point, the nearest polyline within range D,
  *        where a polyline's distance is the minimum point-segment distance over its
