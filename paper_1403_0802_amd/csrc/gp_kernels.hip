@@ -1079,16 +1079,18 @@ __device__ void p2p64_item(const RefineArgs &a, const Item it, SegRec64 *lds, in
 //  * otherwise (a three-way near-tie): the point goes to the FP64 recheck queue.
 // Reported distances are therefore always FP64 values.
 
+// U = (u.x, u.y, -(m-c).u, h) * scale and R = -(m-c).v * scale; v = (-u.y, u.x) comes
+// from U through the FMA's negate modifier, so a segment costs 20 bytes of LDS.
 __device__ __forceinline__ uint32_t seg_d2_bits(float px, float py, const float4 U,
-                                                const float4 V) {
+                                                const float R) {
   const float s = fmaf(px, U.x, fmaf(py, U.y, U.z));
-  const float r = fmaf(px, V.x, fmaf(py, V.y, V.z));
+  const float r = fmaf(px, -U.y, fmaf(py, U.x, R));
   const float e = __builtin_amdgcn_fmed3f(fabsf(s) - U.w, 0.0f, 1.0f);
   return __float_as_uint(fmaf(e, e, r * r));
 }
 
 template <int PPL, int W>
-__device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, float4 *ldsV,
+__device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, float *ldsV,
                             int2 *tab, float *red) {
   const int tid = (int)threadIdx.x;
   const uint32_t lane = lane_id();
@@ -1140,7 +1142,7 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
         const double sC = F.z + (cx * F.x + cy * F.y);
         const double rC = F.w + (cy * F.x - cx * F.y);
         ldsU[filled + t] = make_float4(G.x, G.y, (float)(sC * sc), G.z);
-        ldsV[filled + t] = make_float4(-G.y, G.x, (float)(rC * sc), 0.0f);
+        ldsV[filled + t] = (float)(rC * sc);
         // error bound and "near the cell" test, in distance units
         const float fs = fabsf((float)sC), fr = fabsf((float)rC);
         const float es = 48.0f * 0x1p-24f * (hb * 1.4143f + sqrtf(fs * fs + fr * fr) + G.w);
@@ -1164,29 +1166,39 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
       const int end = te.y & 0x7fffffff;
       int t = start;
       for (; t + 2 <= end; t += 2) {
-        const float4 u0 = ldsU[t], v0 = ldsV[t], u1 = ldsU[t + 1], v1 = ldsV[t + 1];
+        const float4 u0 = ldsU[t], u1 = ldsU[t + 1];
+        const float2 v01 = *(const float2 *)&ldsV[t];
 #pragma unroll
         for (int j = 0; j < PPL; ++j)
-          pm[j] = min(pm[j], min(seg_d2_bits(px[j], py[j], u0, v0),
-                                 seg_d2_bits(px[j], py[j], u1, v1)));
+          pm[j] = min(pm[j], min(seg_d2_bits(px[j], py[j], u0, v01.x),
+                                 seg_d2_bits(px[j], py[j], u1, v01.y)));
       }
       if (t < end) {
-        const float4 u0 = ldsU[t], v0 = ldsV[t];
+        const float4 u0 = ldsU[t];
+        const float v0 = ldsV[t];
 #pragma unroll
         for (int j = 0; j < PPL; ++j) pm[j] = min(pm[j], seg_d2_bits(px[j], py[j], u0, v0));
       }
       if (!(te.y & (int)0x80000000)) {
+        // merge the polyline into the running top three; skipped when it cannot enter
+        // any lane's top three (the common case once the near polylines are seen)
+        bool any = false;
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) {
-          if (pm[j] < b1[j]) {
-            b3[j] = b2[j]; b2[j] = b1[j]; f2[j] = f1[j]; b1[j] = pm[j]; f1[j] = f;
-          } else if (pm[j] < b2[j]) {
-            b3[j] = b2[j]; b2[j] = pm[j]; f2[j] = f;
-          } else if (pm[j] < b3[j]) {
-            b3[j] = pm[j];
+        for (int j = 0; j < PPL; ++j) any |= pm[j] < b3[j];
+        if (ballot(any)) {
+#pragma unroll
+          for (int j = 0; j < PPL; ++j) {
+            if (pm[j] < b1[j]) {
+              b3[j] = b2[j]; b2[j] = b1[j]; f2[j] = f1[j]; b1[j] = pm[j]; f1[j] = f;
+            } else if (pm[j] < b2[j]) {
+              b3[j] = b2[j]; b2[j] = pm[j]; f2[j] = f;
+            } else if (pm[j] < b3[j]) {
+              b3[j] = pm[j];
+            }
           }
-          pm[j] = INFB;
         }
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) pm[j] = INFB;
       }
       start = end;
     }
@@ -1220,7 +1232,9 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
       for (int c = 0; c < ncand; ++c) {
         const int32_t f = c == 0 ? f1[j] : f2[j];
         double pd = INFINITY;
-        for (int32_t e = a.eoff[f]; e < a.eoff[f + 1]; ++e) {
+        const int32_t e1 = a.eoff[f + 1];
+#pragma unroll 2
+        for (int32_t e = a.eoff[f]; e < e1; ++e) {
           const double4 r = a.edge64[e];
           pd = fmin(pd, seg_d2_64(p.x, p.y, r.x, r.y, r.z, r.w));
         }
@@ -1297,7 +1311,7 @@ __global__ __launch_bounds__(64 * W) void k_p2pmix(RefineArgs a, int persistent)
   __shared__ uint32_t s_item;
   __shared__ float red[4];
   float4 *U = (float4 *)smem;
-  float4 *V = U + a.edge_chunk;
+  float *V = (float *)(U + a.edge_chunk);
   int2 *tab = (int2 *)(V + a.edge_chunk);
   const uint32_t n_items = *a.n_items;
   uint32_t it = persistent ? (W == 1 ? next_item(a) : next_item_wg(a, &s_item)) : blockIdx.x;
@@ -1312,7 +1326,7 @@ static size_t refine_lds_bytes(gp_kind kind, gp_precision prec, int ec) {
   if (kind == GP_PIP)
     return prec == GP_FP64 ? (size_t)ec * sizeof(PipRec64) : (size_t)ec * (16 + 16 + 4);
   return prec == GP_FP64 ? (size_t)ec * (sizeof(SegRec64) + sizeof(int2))
-                         : (size_t)ec * (16 + 16 + sizeof(int2));
+                         : (size_t)ec * (16 + 4 + sizeof(int2));
 }
 
 #define GP_DISPATCH(KERNEL, PPLV, ...)                                             \

@@ -1,0 +1,136 @@
+// Measurement probes for the roofline: sustained vector FP32 / FP64 FMA rate, LDS
+// broadcast-read rate, and the P2P inner-loop instruction mix on register data.  Used by
+// bench.py to report the peaks the refinement kernels are judged against; not part of
+// the join itself.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gp_internal.h"
+
+namespace gp {
+gp_status set_error(gp_status code, const char *fmt, ...);
+}
+using namespace gp;
+
+namespace {
+
+// 8 independent FMA chains per lane; the result is stored so nothing is dead code.
+__global__ __launch_bounds__(256) void k_fma_f32(float *out, int iters, float a, float b) {
+  float x0 = threadIdx.x * 1e-7f, x1 = x0 + 1.f, x2 = x0 + 2.f, x3 = x0 + 3.f;
+  float x4 = x0 + 4.f, x5 = x0 + 5.f, x6 = x0 + 6.f, x7 = x0 + 7.f;
+  for (int i = 0; i < iters; ++i) {
+    x0 = fmaf(x0, a, b); x1 = fmaf(x1, a, b); x2 = fmaf(x2, a, b); x3 = fmaf(x3, a, b);
+    x4 = fmaf(x4, a, b); x5 = fmaf(x5, a, b); x6 = fmaf(x6, a, b); x7 = fmaf(x7, a, b);
+  }
+  out[blockIdx.x * blockDim.x + threadIdx.x] = x0 + x1 + x2 + x3 + x4 + x5 + x6 + x7;
+}
+
+__global__ __launch_bounds__(256) void k_fma_f64(double *out, int iters, double a, double b) {
+  double x0 = threadIdx.x * 1e-7, x1 = x0 + 1., x2 = x0 + 2., x3 = x0 + 3.;
+  double x4 = x0 + 4., x5 = x0 + 5., x6 = x0 + 6., x7 = x0 + 7.;
+  for (int i = 0; i < iters; ++i) {
+    x0 = fma(x0, a, b); x1 = fma(x1, a, b); x2 = fma(x2, a, b); x3 = fma(x3, a, b);
+    x4 = fma(x4, a, b); x5 = fma(x5, a, b); x6 = fma(x6, a, b); x7 = fma(x7, a, b);
+  }
+  out[blockIdx.x * blockDim.x + threadIdx.x] = x0 + x1 + x2 + x3 + x4 + x5 + x6 + x7;
+}
+
+// Every lane reads the same 16 bytes (a broadcast), 4 reads per iteration.
+__global__ __launch_bounds__(256) void k_lds_bcast(float *out, int iters) {
+  __shared__ float4 buf[64];
+  if (threadIdx.x < 64) buf[threadIdx.x] = make_float4(threadIdx.x, 1.f, 2.f, 3.f);
+  __syncthreads();
+  float acc = 0.f;
+  int idx = 0;
+  for (int i = 0; i < iters; ++i) {
+    const float4 a = buf[idx], b = buf[idx + 1], c = buf[idx + 2], d = buf[idx + 3];
+    acc += a.x + b.y + c.z + d.w;
+    // the next address depends on the data just read, so no read can be hoisted
+    idx = (idx + 4 + (int)(a.y + b.y - c.y)) & 31;
+  }
+  out[blockIdx.x * blockDim.x + threadIdx.x] = acc;
+}
+
+__device__ __forceinline__ uint32_t probe_seg(float px, float py, const float4 U, float R) {
+  const float s = fmaf(px, U.x, fmaf(py, U.y, U.z));
+  const float r = fmaf(px, -U.y, fmaf(py, U.x, R));
+  const float e = __builtin_amdgcn_fmed3f(fabsf(s) - U.w, 0.0f, 1.0f);
+  return __float_as_uint(fmaf(e, e, r * r));
+}
+
+// The P2P test on segment constants held in registers (no LDS): the VALU-only cost.
+__global__ __launch_bounds__(256) void k_p2p_mix_regs(uint32_t *out, int iters, float4 U0,
+                                                      float4 U1, float R0, float R1) {
+  float px0 = threadIdx.x * 1e-3f, py0 = blockIdx.x * 1e-3f;
+  float px1 = px0 + 0.5f, py1 = py0 + 0.25f;
+  uint32_t m0 = 0x7f800000u, m1 = 0x7f800000u;
+  for (int i = 0; i < iters; ++i) {
+    m0 = min(m0, min(probe_seg(px0, py0, U0, R0), probe_seg(px0, py0, U1, R1)));
+    m1 = min(m1, min(probe_seg(px1, py1, U0, R0), probe_seg(px1, py1, U1, R1)));
+    // perturb every constant so nothing is loop-invariant (4 extra adds per 4 tests)
+    U0.z += 1e-6f;
+    U1.z -= 1e-6f;
+    R0 += 1e-6f;
+    R1 -= 1e-6f;
+  }
+  out[blockIdx.x * blockDim.x + threadIdx.x] = m0 ^ m1;
+}
+
+}  // namespace
+
+// which: 0 FP32 FMA, 1 FP64 FMA, 2 LDS broadcast reads, 3 P2P test on registers.
+// Returns the achieved rate: FLOP/s (0, 1), broadcast reads per second (2) or tests
+// per second (3).
+extern "C" gp_status gp_probe_rate(int32_t which, int32_t iters, double *rate, float *ms) {
+  if (!rate || iters <= 0 || which < 0 || which > 3)
+    return set_error(GP_E_INVALID_ARG, "bad probe arguments");
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return set_error(GP_E_HIP, "no device");
+  const int blocks = cus * 32, threads = 256;
+  void *buf = nullptr;
+  if (hipMalloc(&buf, (size_t)blocks * threads * 8) != hipSuccess)
+    return set_error(GP_E_OOM, "probe buffer");
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  double work = 0.0;
+  for (int rep = 0; rep < 2; ++rep) {  // first launch warms up
+    (void)hipEventRecord(e0, nullptr);
+    const double nthr = (double)blocks * threads;
+    switch (which) {
+      case 0:
+        hipLaunchKernelGGL(k_fma_f32, dim3(blocks), dim3(threads), 0, nullptr, (float *)buf, iters,
+                           0.999f, 1e-3f);
+        work = nthr * iters * 8 * 2;
+        break;
+      case 1:
+        hipLaunchKernelGGL(k_fma_f64, dim3(blocks), dim3(threads), 0, nullptr, (double *)buf, iters,
+                           0.999, 1e-3);
+        work = nthr * iters * 8 * 2;
+        break;
+      case 2:
+        hipLaunchKernelGGL(k_lds_bcast, dim3(blocks), dim3(threads), 0, nullptr, (float *)buf, iters);
+        work = nthr / 64.0 * iters * 4;  // wave-level broadcast reads
+        break;
+      default:
+        hipLaunchKernelGGL(k_p2p_mix_regs, dim3(blocks), dim3(threads), 0, nullptr,
+                           (uint32_t *)buf, iters, make_float4(0.1f, 0.2f, 0.3f, 0.4f),
+                           make_float4(0.5f, 0.6f, 0.7f, 0.8f), 0.9f, 1.1f);
+        work = nthr * iters * 4;  // point-segment tests
+        break;
+    }
+    (void)hipEventRecord(e1, nullptr);
+  }
+  hipError_t err = hipEventSynchronize(e1);
+  float t = 0.f;
+  (void)hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(buf);
+  if (err != hipSuccess) return set_error(GP_E_HIP, "probe failed: %s", hipGetErrorString(err));
+  *rate = work / (t * 1e-3);
+  if (ms) *ms = t;
+  return GP_OK;
+}

@@ -106,6 +106,7 @@ _SIGS = {
     "gp_get_tuning": ([_P, c_int32, POINTER(gp_tuning)], c_int32),
     "gp_autotune": ([_P, c_int32, c_int64, _P, _P, _P, ctypes.c_size_t, _P, POINTER(gp_tuning),
                      POINTER(c_float)], c_int32),
+    "gp_probe_rate": ([c_int32, c_int32, POINTER(c_double), POINTER(c_float)], c_int32),
     "gp_serve_create": ([_P, _P, POINTER(gp_serve_opts), POINTER(_P)], c_int32),
     "gp_serve_submit": ([_P, c_int32, c_int64, _P, _P, _P, _P, POINTER(c_uint64)], c_int32),
     "gp_serve_poll": ([_P, c_uint64, POINTER(c_int32)], c_int32),
@@ -172,11 +173,12 @@ class Grid:
         self.handle = handle
         self.kind = kind
         self._keep = keep
+        self._lib = lib  # module globals are cleared at interpreter shutdown
 
     def __del__(self):
         h, self.handle = getattr(self, "handle", None), None
-        if h:
-            lib.gp_grid_free(h)
+        if h and getattr(self, "_lib", None) is not None:
+            self._lib.gp_grid_free(h)
 
     def info(self) -> dict:
         inf = gp_grid_info()
@@ -282,6 +284,15 @@ def run(grid: Grid, px, py, prec="fp64", ws=None, stream=None, stats=False):
     return (out_id, out_d, st) if stats else (out_id, out_d)
 
 
+def gp_probe_rate(which: int, iters: int):
+    """(rate, ms) of a measurement probe: 0 FP32 FMA FLOP/s, 1 FP64 FMA FLOP/s,
+    2 LDS broadcast reads/s, 3 mixed P2P tests/s on register data."""
+    r = c_double()
+    ms = c_float()
+    check(lib.gp_probe_rate(int(which), int(iters), ctypes.byref(r), ctypes.byref(ms)))
+    return r.value, ms.value
+
+
 # --------------------------------------------------------------------------- serving
 
 
@@ -347,5 +358,6 @@ class Server:
     close = gp_serve_destroy
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            self.close()
+        h, self.handle = getattr(self, "handle", None), None
+        if h and lib is not None:
+            lib.gp_serve_destroy(h)
