@@ -63,7 +63,7 @@ struct DevBuf {
 // Defaults from autotuning on the configuration-3/4 workloads (gp_autotune re-tunes).
 static gp_tuning default_tuning(gp_kind kind, gp_precision prec) {
   gp_tuning t;
-  t.points_per_lane = (prec == GP_MIXED && kind == GP_P2P) ? 2 : 1;
+  t.points_per_lane = (prec == GP_MIXED && kind == GP_P2P) ? 4 : 1;
   t.edge_chunk = prec == GP_MIXED ? 128 : 256;
   t.wg_per_cu = (prec == GP_MIXED && kind == GP_P2P) ? 32 : 16;
   t.persistent = (prec == GP_MIXED && kind == GP_PIP) ? 0 : 1;

@@ -1091,7 +1091,7 @@ __device__ __forceinline__ uint32_t seg_d2_bits(float px, float py, const float4
 
 template <int PPL, int W>
 __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, float *ldsV,
-                            int2 *tab, float *red) {
+                            int2 *tab, int *slotseg, float *red) {
   const int tid = (int)threadIdx.x;
   const uint32_t lane = lane_id();
   const int wave = (int)(threadIdx.x / GP_WAVE);
@@ -1102,6 +1102,7 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
   const float hb = a.half_box;
   const float T = a.p2p_margin;
   const float near_lim = (float)a.D + T + hb * 1.4143f;
+  const float near_lim2 = near_lim * near_lim * (1.0f + 0x1p-16f);
   const double sc = (double)a.p2p_scale;
   const double inv_sc = 1.0 / sc;
   float px[PPL], py[PPL];
@@ -1125,37 +1126,63 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
     f2[j] = -1;
   }
   float emax = 0.0f;  // per-thread partial of E over the segments this thread staged
+  // Stage one segment into chunk slot t: its frame constants relative to the cell centre
+  // c (s_c = -(m - c).u, r_c = -(m - c).v, scaled), and its share of the error bound E.
+  auto stage = [&](int t, const double4 F, const float4 G) {
+    const double sC = F.z + (cx * F.x + cy * F.y);
+    const double rC = F.w + (cy * F.x - cx * F.y);
+    ldsU[t] = make_float4(G.x, G.y, (float)(sC * sc), G.z);
+    ldsV[t] = (float)(rC * sc);
+    // e_s and the "near the cell" test, in distance units.  The bound carries a factor 4
+    // over the rounding analysis, which also covers the few ulps of the hardware square
+    // root here; "near" compares squares against a limit widened by 2^-16.
+    const float fs = fabsf((float)sC), fr = fabsf((float)rC);
+    const float es =
+        48.0f * 0x1p-24f * (hb * 1.4143f + __builtin_amdgcn_sqrtf(fs * fs + fr * fr) + G.w);
+    const float ex = fmaxf(0.0f, fs - 0.5f * G.w);
+    const bool nearc = !(ex * ex + fr * fr > near_lim2) || !(es <= 0.5f * T);
+    if (nearc) emax = fmaxf(emax, es);
+  };
   int32_t k = a.cand_off[it.cell];
   const int32_t k1 = a.cand_off[it.cell + 1];
   int32_t soff = 0;
+  // Candidate window: lane i of each wave holds candidate kw + i (id, first and end
+  // segment), fetched in one round trip, so planning a chunk issues no dependent loads.
+  int32_t kw = k1, wf = 0, we0 = 0, we1 = 0;
   while (k < k1) {
     __syncthreads();
     int filled = 0, ntab = 0;
     while (k < k1 && filled < EC) {
-      const int32_t f = a.cand_id[k];
-      const int32_t s0 = a.eoff[f] + soff, s1 = a.eoff[f + 1];
-      const int take = (s1 - s0) < (EC - filled) ? (s1 - s0) : (EC - filled);
-      for (int t = tid; t < take; t += GP_WAVE * W) {
-        const double4 F = a.frame64[s0 + t];
-        const float4 G = a.frame32[s0 + t];
-        // centre's frame coordinates: s_c = -(m - c).u, r_c = -(m - c).v
-        const double sC = F.z + (cx * F.x + cy * F.y);
-        const double rC = F.w + (cy * F.x - cx * F.y);
-        ldsU[filled + t] = make_float4(G.x, G.y, (float)(sC * sc), G.z);
-        ldsV[filled + t] = (float)(rC * sc);
-        // error bound and "near the cell" test, in distance units
-        const float fs = fabsf((float)sC), fr = fabsf((float)rC);
-        const float es = 48.0f * 0x1p-24f * (hb * 1.4143f + sqrtf(fs * fs + fr * fr) + G.w);
-        const float ex = fmaxf(0.0f, fs - 0.5f * G.w);
-        const bool nearc = !(sqrtf(ex * ex + fr * fr) > near_lim) || !(es <= 0.5f * T);
-        if (nearc) emax = fmaxf(emax, es);
+      if (k >= kw + GP_WAVE || kw == k1) {
+        kw = k;
+        const int32_t kk = kw + (int)lane;
+        wf = kk < k1 ? a.cand_id[kk] : 0;
+        we0 = a.eoff[wf];
+        we1 = a.eoff[wf + 1];
       }
+      const int q = k - kw;
+      const int32_t f = __builtin_amdgcn_readlane(wf, q);
+      const int32_t s0 = __builtin_amdgcn_readlane(we0, q) + soff;
+      const int32_t s1 = __builtin_amdgcn_readlane(we1, q);
+      const int take = (s1 - s0) < (EC - filled) ? (s1 - s0) : (EC - filled);
+      for (int t = tid; t < take; t += GP_WAVE * W) slotseg[filled + t] = s0 + t;
       filled += take;
       const bool cont = s0 + take < s1;
       if (tid == 0) tab[ntab] = make_int2(f, filled | (cont ? (int)0x80000000 : 0));
       ++ntab;
       if (cont) soff += take;
       else { ++k; soff = 0; }
+    }
+    __syncthreads();
+    // fill the chunk: two slots per thread per step, all four loads issued together
+    for (int t = tid; t < filled; t += 2 * GP_WAVE * W) {
+      const int t2 = t + GP_WAVE * W;
+      const bool two = t2 < filled;
+      const int sa = slotseg[t], sb = slotseg[two ? t2 : t];
+      const double4 Fa = a.frame64[sa], Fb = a.frame64[sb];
+      const float4 Ga = a.frame32[sa], Gb = a.frame32[sb];
+      stage(t, Fa, Ga);
+      if (two) stage(t2, Fb, Gb);
     }
     __syncthreads();
     if (!wave_live) continue;
@@ -1166,12 +1193,14 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
       const int end = te.y & 0x7fffffff;
       int t = start;
       for (; t + 2 <= end; t += 2) {
+        // t can be odd (a polyline starts anywhere in the chunk): two 4-byte reads, not
+        // one misaligned 8-byte read, which the LDS serves at a fraction of the rate
         const float4 u0 = ldsU[t], u1 = ldsU[t + 1];
-        const float2 v01 = *(const float2 *)&ldsV[t];
+        const float v0 = ldsV[t], v1 = ldsV[t + 1];
 #pragma unroll
         for (int j = 0; j < PPL; ++j)
-          pm[j] = min(pm[j], min(seg_d2_bits(px[j], py[j], u0, v01.x),
-                                 seg_d2_bits(px[j], py[j], u1, v01.y)));
+          pm[j] = min(pm[j], min(seg_d2_bits(px[j], py[j], u0, v0),
+                                 seg_d2_bits(px[j], py[j], u1, v1)));
       }
       if (t < end) {
         const float4 u0 = ldsU[t];
@@ -1313,10 +1342,11 @@ __global__ __launch_bounds__(64 * W) void k_p2pmix(RefineArgs a, int persistent)
   float4 *U = (float4 *)smem;
   float *V = (float *)(U + a.edge_chunk);
   int2 *tab = (int2 *)(V + a.edge_chunk);
+  int *slotseg = (int *)(tab + a.edge_chunk);
   const uint32_t n_items = *a.n_items;
   uint32_t it = persistent ? (W == 1 ? next_item(a) : next_item_wg(a, &s_item)) : blockIdx.x;
   while (it < n_items) {
-    p2pmix_item<PPL, W>(a, a.items[it], U, V, tab, red);
+    p2pmix_item<PPL, W>(a, a.items[it], U, V, tab, slotseg, red);
     if (!persistent) break;
     it = W == 1 ? next_item(a) : next_item_wg(a, &s_item);
   }
@@ -1326,7 +1356,7 @@ static size_t refine_lds_bytes(gp_kind kind, gp_precision prec, int ec) {
   if (kind == GP_PIP)
     return prec == GP_FP64 ? (size_t)ec * sizeof(PipRec64) : (size_t)ec * (16 + 16 + 4);
   return prec == GP_FP64 ? (size_t)ec * (sizeof(SegRec64) + sizeof(int2))
-                         : (size_t)ec * (16 + 4 + sizeof(int2));
+                         : (size_t)ec * (16 + 4 + sizeof(int2) + sizeof(int));
 }
 
 #define GP_DISPATCH(KERNEL, PPLV, ...)                                             \
