@@ -1089,9 +1089,22 @@ __device__ __forceinline__ uint32_t seg_d2_bits(float px, float py, const float4
   return __float_as_uint(fmaf(e, e, r * r));
 }
 
+// Segments per unit of the exact-distance pass, and the LDS that pass needs per wave
+// (results, pair descriptors and points of up to two pairs per lane).
+#define P2P_UNIT 16
+#define P2P_EPI_BYTES (2 * GP_WAVE * (8 + 16) + GP_WAVE * 16)
+
+// Orders a wave's LDS accesses: every lane's earlier LDS writes are visible to every
+// lane's later reads (one wave executes its LDS instructions in order; the fence keeps
+// the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <int PPL, int W>
 __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, float *ldsV,
-                            int2 *tab, int *slotseg, float *red) {
+                            int2 *tab, int *slotseg, float *red, unsigned char *epi) {
   const int tid = (int)threadIdx.x;
   const uint32_t lane = lane_id();
   const int wave = (int)(threadIdx.x / GP_WAVE);
@@ -1243,6 +1256,15 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
   if (!wave_live) return;
   const double E = (double)emax;
   const double D = a.D;
+  // Exact FP64 distances of each point's one or two candidate polylines, load-balanced
+  // over the wave: the (point, polyline) pairs are cut into units of P2P_UNIT segments
+  // that the lanes share, and each unit's minimum joins its pair's result by an LDS
+  // atomic minimum.  Non-negative doubles order like their bit patterns, so the result
+  // is the exact minimum over the polyline whatever the order of the units.
+  wave_lds_sync();  // with one wave per item the chunk's LDS is reused without a barrier
+  uint64_t *res = (uint64_t *)(epi + wave * P2P_EPI_BYTES);
+  int4 *pinfo = (int4 *)(res + 2 * GP_WAVE);  // {first seg, end seg, first unit, lane}
+  double2 *pts = (double2 *)(pinfo + 2 * GP_WAVE);
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
     const int idx = wbase + (int)lane + GP_WAVE * j;
@@ -1254,19 +1276,54 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
     // candidates for the answer: f1 alone, or f1 and f2 (every other polyline is
     // provably farther than both); their exact FP64 distances decide
     const int ncand = miss ? 0 : (d2 - d1 > 2.0 * E) ? 1 : (d3 - d1 > 2.0 * E) ? 2 : 3;
-    if (v && (ncand == 1 || ncand == 2)) {
-      const double2 p = a.xy[it.pt_lo + idx];
-      int32_t bid = -1;
-      double best = INFINITY;
-      for (int c = 0; c < ncand; ++c) {
-        const int32_t f = c == 0 ? f1[j] : f2[j];
+    const int nc = (v && (ncand == 1 || ncand == 2)) ? ncand : 0;
+    int32_t s00 = 0, s01 = 0, s10 = 0, s11 = 0;
+    if (nc >= 1) { s00 = a.eoff[f1[j]]; s01 = a.eoff[f1[j] + 1]; }
+    if (nc >= 2) { s10 = a.eoff[f2[j]]; s11 = a.eoff[f2[j] + 1]; }
+    const int u0 = (s01 - s00 + P2P_UNIT - 1) / P2P_UNIT;
+    const int u1 = (s11 - s10 + P2P_UNIT - 1) / P2P_UNIT;
+    const uint32_t pinc = wave_incl_scan((uint32_t)nc);
+    const uint32_t uinc = wave_incl_scan((uint32_t)(u0 + u1));
+    const int npairs = (int)__builtin_amdgcn_readlane(pinc, GP_WAVE - 1);
+    const int nunits = (int)__builtin_amdgcn_readlane(uinc, GP_WAVE - 1);
+    const int pid = (int)pinc - nc, uoff = (int)uinc - (u0 + u1);
+    if (npairs > 0) {
+      if (nc >= 1) {
+        res[pid] = 0x7ff0000000000000ull;  // +inf
+        pinfo[pid] = make_int4(s00, s01, uoff, (int)lane);
+        pts[lane] = a.xy[it.pt_lo + idx];
+      }
+      if (nc >= 2) {
+        res[pid + 1] = 0x7ff0000000000000ull;
+        pinfo[pid + 1] = make_int4(s10, s11, uoff + u0, (int)lane);
+      }
+      wave_lds_sync();
+      for (int u = (int)lane; u < nunits; u += GP_WAVE) {
+        int lo = 0, hi = npairs - 1;  // the last pair whose first unit is <= u
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (pinfo[mid].z <= u) lo = mid;
+          else hi = mid - 1;
+        }
+        const int4 P = pinfo[lo];
+        const double2 p = pts[P.w];
+        const int32_t e0 = P.x + (u - P.z) * P2P_UNIT;
+        const int32_t e1 = min(e0 + P2P_UNIT, P.y);
         double pd = INFINITY;
-        const int32_t e1 = a.eoff[f + 1];
-#pragma unroll 2
-        for (int32_t e = a.eoff[f]; e < e1; ++e) {
+        for (int32_t e = e0; e < e1; ++e) {
           const double4 r = a.edge64[e];
           pd = fmin(pd, seg_d2_64(p.x, p.y, r.x, r.y, r.z, r.w));
         }
+        atomicMin((unsigned long long *)&res[lo], (unsigned long long)__double_as_longlong(pd));
+      }
+      wave_lds_sync();
+    }
+    if (nc) {
+      int32_t bid = -1;
+      double best = INFINITY;
+      for (int c = 0; c < nc; ++c) {
+        const int32_t f = c == 0 ? f1[j] : f2[j];
+        const double pd = __longlong_as_double((long long)res[pid + c]);
         if (pd <= a.D2 && (pd < best || (pd == best && f < bid))) { best = pd; bid = f; }
       }
       const uint32_t o = a.perm[it.pt_lo + idx];
@@ -1278,6 +1335,7 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
       a.out_dist[o] = INFINITY;
     }
     push_recheck(a, v && ncand == 3, (uint32_t)(it.pt_lo + idx));
+    wave_lds_sync();  // the next point slot reuses res/pinfo/pts
   }
 }
 
@@ -1346,17 +1404,20 @@ __global__ __launch_bounds__(64 * W) void k_p2pmix(RefineArgs a, int persistent)
   const uint32_t n_items = *a.n_items;
   uint32_t it = persistent ? (W == 1 ? next_item(a) : next_item_wg(a, &s_item)) : blockIdx.x;
   while (it < n_items) {
-    p2pmix_item<PPL, W>(a, a.items[it], U, V, tab, slotseg, red);
+    p2pmix_item<PPL, W>(a, a.items[it], U, V, tab, slotseg, red, smem);
     if (!persistent) break;
     it = W == 1 ? next_item(a) : next_item_wg(a, &s_item);
   }
 }
 
-static size_t refine_lds_bytes(gp_kind kind, gp_precision prec, int ec) {
+static size_t refine_lds_bytes(gp_kind kind, gp_precision prec, int ec, int W) {
   if (kind == GP_PIP)
     return prec == GP_FP64 ? (size_t)ec * sizeof(PipRec64) : (size_t)ec * (16 + 16 + 4);
-  return prec == GP_FP64 ? (size_t)ec * (sizeof(SegRec64) + sizeof(int2))
-                         : (size_t)ec * (16 + 4 + sizeof(int2) + sizeof(int));
+  if (prec == GP_FP64) return (size_t)ec * (sizeof(SegRec64) + sizeof(int2));
+  // the chunk (segment records, polyline table, slot map), reused by the exact pass
+  const size_t chunk = (size_t)ec * (16 + 4 + sizeof(int2) + sizeof(int));
+  const size_t epi = (size_t)W * P2P_EPI_BYTES;
+  return chunk > epi ? chunk : epi;
 }
 
 #define GP_DISPATCH(KERNEL, PPLV, ...)                                             \
@@ -1386,7 +1447,7 @@ static size_t refine_lds_bytes(gp_kind kind, gp_precision prec, int ec) {
 hipError_t launch_refine(gp_kind kind, gp_precision prec, const RefineArgs &a,
                          const gp_tuning &t, int num_cu, int64_t max_items, hipStream_t s) {
   const int ppl = t.points_per_lane;
-  const size_t lds = refine_lds_bytes(kind, prec, a.edge_chunk);
+
   unsigned grid;
   if (t.persistent) {
     int64_t g = (int64_t)num_cu * t.wg_per_cu;
@@ -1397,6 +1458,7 @@ hipError_t launch_refine(gp_kind kind, gp_precision prec, const RefineArgs &a,
   }
   const int pers = t.persistent ? 1 : 0;
   const int W = kind == GP_P2P ? t.waves_per_item : 1;
+  const size_t lds = refine_lds_bytes(kind, prec, a.edge_chunk, W);
   const dim3 blk(64 * W);
   if (kind == GP_PIP && prec == GP_FP64)
     GP_DISPATCH(k_pip64, ppl, dim3(grid), blk, lds, s, a, pers);
