@@ -241,6 +241,9 @@ extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
     GP_TRY_HIP_G(hipMalloc(&g->d_frame32, ns * sizeof(float4)));
     GP_TRY_HIP_G(launch_build_frames(g->d_edge64, (int32_t)nedges, g->p2p_scale, g->d_frame64,
                                      g->d_frame32, s));
+    const size_t nb = (ns + P2P_BLOCK - 1) / P2P_BLOCK;
+    GP_TRY_HIP_G(hipMalloc(&g->d_circ, nb * sizeof(double4)));
+    GP_TRY_HIP_G(launch_build_circles(g->d_edge64, (int32_t)nedges, g->d_circ, s));
   }
 
   // extent
@@ -332,6 +335,7 @@ extern "C" void gp_grid_free(gp_grid *g) {
   (void)hipFree(g->d_k32);
   (void)hipFree(g->d_frame64);
   (void)hipFree(g->d_frame32);
+  (void)hipFree(g->d_circ);
   (void)hipFree(g->d_cand_off);
   (void)hipFree(g->d_cand_id);
   (void)hipFree(g->d_cell_edges);
@@ -481,6 +485,7 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   a.k32 = g->d_k32;
   a.frame64 = g->d_frame64;
   a.frame32 = g->d_frame32;
+  a.circ = g->d_circ;
   a.x0 = g->x0;
   a.y0 = g->y0;
   a.cs = g->cs;

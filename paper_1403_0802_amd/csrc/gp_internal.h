@@ -10,6 +10,9 @@
 
 namespace gp {
 
+// Consecutive segments covered by one bounding circle of the P2P exact-distance pass.
+constexpr int P2P_BLOCK = 8;
+
 // Work item of the refinement: a grid cell and a chunk of its (sorted) points.  The
 // cell's whole candidate list is refined by one workgroup, so per-point results never
 // need a cross-workgroup merge.
@@ -34,6 +37,7 @@ struct RefineArgs {
   const float *k32;          // PIP: fl32(w/h), 0 for horizontal edges
   const double4 *frame64;    // P2P: (u.x, u.y, -m.u, -m.v) of each segment, absolute m
   const float4 *frame32;     // P2P: (u.x*scale, u.y*scale, |d|/2*scale, |d|)
+  const double4 *circ;       // P2P: per block of P2P_BLOCK segments (centre x, y, radius, 0)
   double x0, y0, cs;
   int32_t nx, ncells;
   double D, D2, D2_next;     // P2P: D, fl(D*D), the smallest double above fl(D*D)
@@ -65,6 +69,7 @@ struct Grid {
   float *d_k32;
   double4 *d_frame64;
   float4 *d_frame32;
+  double4 *d_circ;
   int32_t *d_cand_off;
   int32_t *d_cand_id;
   int64_t *d_cell_edges;  // [ncells] sum of nedges over the cell's candidates
@@ -114,6 +119,8 @@ hipError_t launch_build_edges(const int32_t *ring_vert_off, const int32_t *featu
                               int32_t *eoff, hipStream_t s);
 hipError_t launch_build_frames(const double4 *seg64, int32_t nseg, float scale,
                                double4 *frame64, float4 *frame32, hipStream_t s);
+hipError_t launch_build_circles(const double4 *seg64, int32_t nseg, double4 *circ,
+                                hipStream_t s);
 hipError_t launch_mbb(const int32_t *ring_vert_off, const int32_t *feature_ring_off,
                       const double *x, const double *y, int32_t nf, gp_kind kind, double D,
                       double cs, double *mbb, hipStream_t s);

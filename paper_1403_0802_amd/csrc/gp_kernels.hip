@@ -375,6 +375,40 @@ hipError_t launch_build_frames(const double4 *seg64, int32_t nseg, float scale,
   return hipGetLastError();
 }
 
+// Bounding circle of each block of P2P_BLOCK consecutive segments (blocks may span two
+// polylines; the circle still contains every segment of the block): centre of the
+// endpoints' box, radius the largest endpoint distance, widened by 2^-40 relative so
+// that the FP64 rounding of its computation cannot make it too small.
+__global__ void k_build_circles(const double4 *seg, int32_t nseg, double4 *circ) {
+  const int32_t nb = (nseg + P2P_BLOCK - 1) / P2P_BLOCK;
+  for (int32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
+    const int32_t e0 = b * P2P_BLOCK, e1 = min(e0 + P2P_BLOCK, nseg);
+    double lx = INFINITY, ly = INFINITY, hx = -INFINITY, hy = -INFINITY;
+    for (int32_t e = e0; e < e1; ++e) {
+      const double4 r = seg[e];
+      lx = fmin(lx, fmin(r.x, r.z)); hx = fmax(hx, fmax(r.x, r.z));
+      ly = fmin(ly, fmin(r.y, r.w)); hy = fmax(hy, fmax(r.y, r.w));
+    }
+    const double cx = 0.5 * (lx + hx), cy = 0.5 * (ly + hy);
+    double r2 = 0.0;
+    for (int32_t e = e0; e < e1; ++e) {
+      const double4 r = seg[e];
+      const double ax = r.x - cx, ay = r.y - cy, bx = r.z - cx, by = r.w - cy;
+      r2 = fmax(r2, fmax(ax * ax + ay * ay, bx * bx + by * by));
+    }
+    circ[b] = make_double4(cx, cy, sqrt(r2) * (1.0 + 0x1p-40), 0.0);
+  }
+}
+
+hipError_t launch_build_circles(const double4 *seg64, int32_t nseg, double4 *circ,
+                                hipStream_t s) {
+  if (nseg <= 0) return hipSuccess;
+  const int32_t nb = (nseg + P2P_BLOCK - 1) / P2P_BLOCK;
+  hipLaunchKernelGGL(k_build_circles, dim3(grid_for(nb, 256, 8192)), dim3(256), 0, s, seg64,
+                     nseg, circ);
+  return hipGetLastError();
+}
+
 // Feature MBB over all of its vertices; P2P expands by D; both pad by cs*2^-20.
 __global__ void k_mbb(const int32_t *rvo, const int32_t *fro, const double *x, const double *y,
                       int32_t nf, int kind, double D, double cs, double *mbb) {
@@ -1089,10 +1123,9 @@ __device__ __forceinline__ uint32_t seg_d2_bits(float px, float py, const float4
   return __float_as_uint(fmaf(e, e, r * r));
 }
 
-// Segments per unit of the exact-distance pass, and the LDS that pass needs per wave
-// (results, pair descriptors and points of up to two pairs per lane).
-#define P2P_UNIT 16
-#define P2P_EPI_BYTES (2 * GP_WAVE * (8 + 16) + GP_WAVE * 16)
+// LDS of the exact-distance pass per wave: for up to two pairs per lane the result,
+// descriptor and threshold, the lanes' points, and a queue of 128 (pair, block) entries.
+#define P2P_EPI_BYTES (2 * GP_WAVE * (8 + 16 + 8 + 8) + GP_WAVE * 16)
 
 // Orders a wave's LDS accesses: every lane's earlier LDS writes are visible to every
 // lane's later reads (one wave executes its LDS instructions in order; the fence keeps
@@ -1256,15 +1289,43 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
   if (!wave_live) return;
   const double E = (double)emax;
   const double D = a.D;
-  // Exact FP64 distances of each point's one or two candidate polylines, load-balanced
-  // over the wave: the (point, polyline) pairs are cut into units of P2P_UNIT segments
-  // that the lanes share, and each unit's minimum joins its pair's result by an LDS
-  // atomic minimum.  Non-negative doubles order like their bit patterns, so the result
-  // is the exact minimum over the polyline whatever the order of the units.
+  // Exact FP64 distances of each point's one or two candidate polylines.  With d_c the
+  // FP32-derived distance of candidate c, the exact minimum over its segments is at most
+  // d_c + E' with E' = max(E, T/2): every staged segment's error is at most E (near the
+  // cell) or T/2 (otherwise it would count as near).  A block of P2P_BLOCK segments
+  // whose bounding circle lies farther than d_c + E' cannot hold the minimum.  The wave tests the blocks of all its (point, polyline) pairs
+  // together, queues the blocks that pass in LDS, and evaluates them 64 at a time, one
+  // per lane; each block's minimum joins its pair's result by an LDS atomic minimum.
+  // Non-negative doubles order like their bit patterns, so the result is the exact
+  // minimum over the polyline's segments whatever the order of the blocks.
+  const double Ep = fmax(E, 0.5 * (double)T);
   wave_lds_sync();  // with one wave per item the chunk's LDS is reused without a barrier
-  uint64_t *res = (uint64_t *)(epi + wave * P2P_EPI_BYTES);
-  int4 *pinfo = (int4 *)(res + 2 * GP_WAVE);  // {first seg, end seg, first unit, lane}
-  double2 *pts = (double2 *)(pinfo + 2 * GP_WAVE);
+  unsigned char *wepi = epi + wave * P2P_EPI_BYTES;
+  uint64_t *res = (uint64_t *)wepi;                  // [2*64] result bits per pair
+  int4 *pinfo = (int4 *)(res + 2 * GP_WAVE);         // [2*64] {first seg, end seg, first unit, lane}
+  double *pthr = (double *)(pinfo + 2 * GP_WAVE);    // [2*64] d_c + E'
+  double2 *pts = (double2 *)(pthr + 2 * GP_WAVE);    // [64] the lanes' points
+  int2 *uq = (int2 *)(pts + GP_WAVE);                // [2*64] queued (pair, block)
+  auto unit_pair = [&](int u, int npairs) {  // the last pair whose first unit is <= u
+    int lo = 0, hi = npairs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pinfo[mid].z <= u) lo = mid;
+      else hi = mid - 1;
+    }
+    return lo;
+  };
+  auto eval_block = [&](int2 qb) {
+    const int4 P = pinfo[qb.x];
+    const double2 p = pts[P.w];
+    const int32_t e0 = max(P.x, qb.y * P2P_BLOCK), e1 = min(P.y, (qb.y + 1) * P2P_BLOCK);
+    double pd = INFINITY;
+    for (int32_t e = e0; e < e1; ++e) {
+      const double4 r = a.edge64[e];
+      pd = fmin(pd, seg_d2_64(p.x, p.y, r.x, r.y, r.z, r.w));
+    }
+    atomicMin((unsigned long long *)&res[qb.x], (unsigned long long)__double_as_longlong(pd));
+  };
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
     const int idx = wbase + (int)lane + GP_WAVE * j;
@@ -1280,8 +1341,9 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
     int32_t s00 = 0, s01 = 0, s10 = 0, s11 = 0;
     if (nc >= 1) { s00 = a.eoff[f1[j]]; s01 = a.eoff[f1[j] + 1]; }
     if (nc >= 2) { s10 = a.eoff[f2[j]]; s11 = a.eoff[f2[j] + 1]; }
-    const int u0 = (s01 - s00 + P2P_UNIT - 1) / P2P_UNIT;
-    const int u1 = (s11 - s10 + P2P_UNIT - 1) / P2P_UNIT;
+    // blocks overlapped by a pair's segments (every polyline has at least one segment)
+    const int u0 = nc >= 1 ? (s01 - 1) / P2P_BLOCK - s00 / P2P_BLOCK + 1 : 0;
+    const int u1 = nc >= 2 ? (s11 - 1) / P2P_BLOCK - s10 / P2P_BLOCK + 1 : 0;
     const uint32_t pinc = wave_incl_scan((uint32_t)nc);
     const uint32_t uinc = wave_incl_scan((uint32_t)(u0 + u1));
     const int npairs = (int)__builtin_amdgcn_readlane(pinc, GP_WAVE - 1);
@@ -1291,31 +1353,46 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
       if (nc >= 1) {
         res[pid] = 0x7ff0000000000000ull;  // +inf
         pinfo[pid] = make_int4(s00, s01, uoff, (int)lane);
+        pthr[pid] = d1 + Ep;
         pts[lane] = a.xy[it.pt_lo + idx];
       }
       if (nc >= 2) {
         res[pid + 1] = 0x7ff0000000000000ull;
         pinfo[pid + 1] = make_int4(s10, s11, uoff + u0, (int)lane);
+        pthr[pid + 1] = d2 + Ep;
       }
       wave_lds_sync();
-      for (int u = (int)lane; u < nunits; u += GP_WAVE) {
-        int lo = 0, hi = npairs - 1;  // the last pair whose first unit is <= u
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (pinfo[mid].z <= u) lo = mid;
-          else hi = mid - 1;
+      int qn = 0;  // queued blocks (uniform)
+      for (int ub = 0; ub < nunits; ub += GP_WAVE) {
+        const int u = ub + (int)lane;
+        bool pass = false;
+        int2 qb = make_int2(0, 0);
+        if (u < nunits) {
+          const int q = unit_pair(u, npairs);
+          const int4 P = pinfo[q];
+          const int blk = P.x / P2P_BLOCK + (u - P.z);
+          const double2 p = pts[P.w];
+          const double4 C = a.circ[blk];
+          const double dx = p.x - C.x, dy = p.y - C.y;
+          const double R = (C.z + pthr[q]) * (1.0 + 0x1p-40);
+          pass = !(dx * dx + dy * dy > R * R);
+          qb = make_int2(q, blk);
         }
-        const int4 P = pinfo[lo];
-        const double2 p = pts[P.w];
-        const int32_t e0 = P.x + (u - P.z) * P2P_UNIT;
-        const int32_t e1 = min(e0 + P2P_UNIT, P.y);
-        double pd = INFINITY;
-        for (int32_t e = e0; e < e1; ++e) {
-          const double4 r = a.edge64[e];
-          pd = fmin(pd, seg_d2_64(p.x, p.y, r.x, r.y, r.z, r.w));
+        const uint64_t m = ballot(pass);
+        if (pass) uq[qn + (int)__popcll(m & lanemask_lt())] = qb;
+        qn += (int)__popcll(m);
+        wave_lds_sync();
+        if (qn >= GP_WAVE) {
+          eval_block(uq[lane]);
+          const int rest = qn - GP_WAVE;
+          const int2 tail = (int)lane < rest ? uq[GP_WAVE + lane] : make_int2(0, 0);
+          wave_lds_sync();
+          if ((int)lane < rest) uq[lane] = tail;
+          qn = rest;
+          wave_lds_sync();
         }
-        atomicMin((unsigned long long *)&res[lo], (unsigned long long)__double_as_longlong(pd));
       }
+      if ((int)lane < qn) eval_block(uq[lane]);
       wave_lds_sync();
     }
     if (nc) {
@@ -1335,7 +1412,7 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
       a.out_dist[o] = INFINITY;
     }
     push_recheck(a, v && ncand == 3, (uint32_t)(it.pt_lo + idx));
-    wave_lds_sync();  // the next point slot reuses res/pinfo/pts
+    wave_lds_sync();  // the next point slot reuses the pass's LDS
   }
 }
 

@@ -1,7 +1,7 @@
 """HIP path vs the CPU oracle, element by element, through the C ABI.
 
-Bars: grid pairing, PIP ids and P2P ids bit-exact; P2P distances bitwise for the FP64
-form and within 1e-3 (absolute, input units) for the mixed form.
+Bars: grid pairing, PIP ids and P2P ids bit-exact; P2P distances bitwise equal to the
+oracle's in both forms (the mixed form recomputes its winners' distances in FP64).
 """
 import math
 
@@ -314,6 +314,38 @@ def test_p2p_ties_range_and_degenerate_segments(gp):
     og = oracle.build_grid(g, params)
     want_id, want_d = oracle.p2p(g, px, py, params.radius_D, og)
     assert want_id[:5].tolist() == [0, 0, 2, -1, 4]
+    grid = gp.gp_build_grid("p2p", g, params)
+    for prec in ("fp64", "mixed"):
+        gid, gd = run_gpu(gp, grid, px, py, prec)
+        check_p2p(gid, gd, want_id, want_d, prec, prec)
+
+
+def test_p2p_exact_pass_many_equidistant_segments(gp):
+    """Closed 400-gon polylines around points near their centres: nearly every segment
+    of the nearest polyline is within the filter margin of the best, so the exact pass
+    queues and evaluates most blocks of every pair (many queue drains per wave)."""
+    say("p2p equidistant rings")
+    rng = np.random.default_rng(8)
+    centres = [(15.0 + 30.0 * i, 15.0 + 30.0 * j) for i in range(5) for j in range(4)]
+    lines = []
+    for k, (cx, cy) in enumerate(centres):
+        r = 5.0 + 0.25 * (k % 3)
+        t = np.linspace(0.0, 2.0 * np.pi, 401) + 0.01 * k
+        t[-1] = t[0]  # closed: the last vertex repeats the first
+        lines.append(list(zip(cx + r * np.cos(t), cy + r * np.sin(t))))
+        # a slightly larger concentric ring: a second candidate at almost the same distance
+        lines.append(list(zip(cx + (r + 1e-4) * np.cos(t), cy + (r + 1e-4) * np.sin(t))))
+    g = pins.polylines(lines)
+    params = synth.GridParams(cell_size=2.0, radius_D=10.0, x0=0.0, y0=0.0, nx=80, ny=64)
+    c = np.array(centres)
+    pick = rng.integers(0, len(c), 60_000)
+    rad = 0.5 * np.sqrt(rng.uniform(0, 1, len(pick)))
+    ang = rng.uniform(0, 2 * np.pi, len(pick))
+    px = np.concatenate([c[:, 0], c[pick, 0] + rad * np.cos(ang), rng.uniform(0, 160, 40_000)])
+    py = np.concatenate([c[:, 1], c[pick, 1] + rad * np.sin(ang), rng.uniform(0, 128, 40_000)])
+    og = oracle.build_grid(g, params)
+    want_id, want_d = oracle.p2p(g, px, py, params.radius_D, og)
+    assert np.all(want_id[:len(c)] >= 0)
     grid = gp.gp_build_grid("p2p", g, params)
     for prec in ("fp64", "mixed"):
         gid, gd = run_gpu(gp, grid, px, py, prec)
