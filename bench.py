@@ -268,11 +268,22 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if not args.no_autotune:
-        # the autotuner times each kernel configuration on a sample of the workload
-        n_s = min(x3.numel(), 4_000_000)
-        log("[bench] autotune pip", gp.gp_autotune(grid3, prec, x3[:n_s], y3[:n_s], ws3))
-        n_s = min(x4.numel(), 8_000_000)
-        log("[bench] autotune p2p", gp.gp_autotune(grid4, prec, x4[:n_s], y4[:n_s], ws4))
+        # The autotuner times each kernel configuration on a sample of the workload.  The
+        # sample keeps every point of one cell in 16 (cells whose column and row are both
+        # multiples of 4), so points per cell -- what the tile shape trades against -- are
+        # those of the full workload.
+        def cell_sample(x, y, p):
+            cx = torch.floor((x - p.x0) / p.cell_size).to(torch.int64)
+            cy = torch.floor((y - p.y0) / p.cell_size).to(torch.int64)
+            m = (cx % 4 == 0) & (cy % 4 == 0)
+            return x[m].contiguous(), y[m].contiguous()
+        sx, sy = cell_sample(x3, y3, p3)
+        log("[bench] autotune pip on", sx.numel(), "points",
+            gp.gp_autotune(grid3, prec, sx, sy, ws3))
+        sx, sy = cell_sample(x4, y4, p4)
+        log("[bench] autotune p2p on", sx.numel(), "points",
+            gp.gp_autotune(grid4, prec, sx, sy, ws4))
+        del sx, sy
 
     def step(stats):
         a = gp.gp_pip(grid3, x3, y3, id3, prec, ws3, stream, stats)
