@@ -336,6 +336,16 @@ def main():
         "grid_build_ms": build_ms,
         "tuning": {"pip": gp.gp_get_tuning(grid3, prec), "p2p": gp.gp_get_tuning(grid4, prec)},
     }
+    # Measured ceilings of this GPU (micro-kernels in the library): FP32 FMA with VGPR
+    # operands (the form of the refinement loops) and with an SGPR operand, FP64 FMA, and
+    # the mixed P2P test's instruction mix on register data.
+    probes = {}
+    for key, which, iters in (("fp32_fma_vgpr_tflops", 0, 20000), ("fp32_fma_sgpr_tflops", 4, 20000),
+                              ("fp64_fma_tflops", 1, 10000), ("p2p_test_regs_tests_per_s", 3, 5000)):
+        r, _ = gp.gp_probe_rate(which, iters)
+        probes[key] = r / 1e12 if key.endswith("tflops") else r
+    probes["p2p_refine_vs_regs_probe"] = (tests_p2p / (p2p_ref / 1e3)) / probes["p2p_test_regs_tests_per_s"]
+    detail["probes"] = probes
     # the FP64 form on the same inputs, for comparison
     if not args.no_fp64:
         del ws3, ws4

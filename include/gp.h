@@ -187,9 +187,11 @@ gp_status gp_autotune(gp_grid *grid, gp_precision prec, int64_t n, const double 
                       gp_tuning *best, float *best_ms);
 
 /* Measurement probe (not part of the join): sustained rate on the current device of
- * which = 0: FP32 FMA (FLOP/s), 1: FP64 FMA (FLOP/s), 2: LDS broadcast 16-byte reads
- * (wave reads/s), 3: the mixed P2P point-segment test on register data (tests/s).
- * `iters` sets the loop length; *ms receives the kernel time.  Synchronous. */
+ * which = 0: FP32 FMA with every operand in a VGPR (FLOP/s), 1: FP64 FMA (FLOP/s),
+ * 2: LDS broadcast 16-byte reads (wave reads/s), 3: the mixed P2P point-segment test on
+ * register data (tests/s), 4: FP32 FMA with one SGPR operand (FLOP/s).  `iters` sets the
+ * loop length; *ms receives the kernel time.  Synchronous; GP_E_INVALID_ARG for other
+ * `which` or iters <= 0. */
 gp_status gp_probe_rate(int32_t which, int32_t iters, double *rate, float *ms);
 
 /* ---------------------------------------------------------------- serving */

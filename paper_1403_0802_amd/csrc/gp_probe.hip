@@ -1,5 +1,6 @@
-// Measurement probes for the roofline: sustained vector FP32 / FP64 FMA rate, LDS
-// broadcast-read rate, and the P2P inner-loop instruction mix on register data.  Used by
+// Measurement probes for the roofline: sustained vector FP32 / FP64 FMA rate (FP32 with
+// VGPR operands and with an SGPR operand), LDS broadcast-read rate, and the P2P
+// inner-loop instruction mix on register data.  Used by
 // bench.py to report the peaks the refinement kernels are judged against; not part of
 // the join itself.
 #include <hip/hip_runtime.h>
@@ -15,14 +16,25 @@ using namespace gp;
 namespace {
 
 // 8 independent FMA chains per lane; the result is stored so nothing is dead code.
+// VGPR_OPS: every operand in a VGPR (or an inline literal), the form the refinement
+// kernels' inner loops take; otherwise one operand comes from an SGPR, which gfx950
+// issues at about half the rate.
+template <bool VGPR_OPS>
 __global__ __launch_bounds__(256) void k_fma_f32(float *out, int iters, float a, float b) {
-  float x0 = threadIdx.x * 1e-7f, x1 = x0 + 1.f, x2 = x0 + 2.f, x3 = x0 + 3.f;
-  float x4 = x0 + 4.f, x5 = x0 + 5.f, x6 = x0 + 6.f, x7 = x0 + 7.f;
-  for (int i = 0; i < iters; ++i) {
-    x0 = fmaf(x0, a, b); x1 = fmaf(x1, a, b); x2 = fmaf(x2, a, b); x3 = fmaf(x3, a, b);
-    x4 = fmaf(x4, a, b); x5 = fmaf(x5, a, b); x6 = fmaf(x6, a, b); x7 = fmaf(x7, a, b);
+  float x[8], y[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    x[c] = threadIdx.x * 1e-7f + c;
+    y[c] = VGPR_OPS ? 0.5f + 1e-3f * (float)(threadIdx.x & 7) + 1e-4f * c : a;
   }
-  out[blockIdx.x * blockDim.x + threadIdx.x] = x0 + x1 + x2 + x3 + x4 + x5 + x6 + x7;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) x[c] = VGPR_OPS ? fmaf(x[c], y[c], x[c ^ 1]) : fmaf(x[c], a, b);
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) s += x[c];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
 __global__ __launch_bounds__(256) void k_fma_f64(double *out, int iters, double a, double b) {
@@ -35,20 +47,29 @@ __global__ __launch_bounds__(256) void k_fma_f64(double *out, int iters, double 
   out[blockIdx.x * blockDim.x + threadIdx.x] = x0 + x1 + x2 + x3 + x4 + x5 + x6 + x7;
 }
 
-// Every lane reads the same 16 bytes (a broadcast), 4 reads per iteration.
+// LDS broadcast: 4 x ds_read_b128 per iteration, every lane of a wave at the same
+// address (within a 4 KB buffer); the wait for the reads is inside the same asm block.
 __global__ __launch_bounds__(256) void k_lds_bcast(float *out, int iters) {
-  __shared__ float4 buf[64];
-  if (threadIdx.x < 64) buf[threadIdx.x] = make_float4(threadIdx.x, 1.f, 2.f, 3.f);
+  __shared__ float4 buf[256];
+  buf[threadIdx.x] = make_float4(threadIdx.x, 1.f, 2.f, 3.f);
   __syncthreads();
-  float acc = 0.f;
-  int idx = 0;
+  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
+  const uint32_t base = (threadIdx.x / 64) * 8 * 16;
   for (int i = 0; i < iters; ++i) {
-    const float4 a = buf[idx], b = buf[idx + 1], c = buf[idx + 2], d = buf[idx + 3];
-    acc += a.x + b.y + c.z + d.w;
-    // the next address depends on the data just read, so no read can be hoisted
-    idx = (idx + 4 + (int)(a.y + b.y - c.y)) & 31;
+    const uint32_t addr = base + (uint32_t)(i & 3) * 256u;  // + 48 + 16 < 4096
+    float4 p, q, r, u;
+    asm volatile(
+        "ds_read_b128 %0, %4\n"
+        "ds_read_b128 %1, %4 offset:16\n"
+        "ds_read_b128 %2, %4 offset:32\n"
+        "ds_read_b128 %3, %4 offset:48\n"
+        "s_waitcnt lgkmcnt(0)\n"
+        : "=v"(p), "=v"(q), "=v"(r), "=v"(u)
+        : "v"(addr)
+        : "memory");
+    acc0 += p.x + p.w; acc1 += q.y + q.z; acc2 += r.z + r.x; acc3 += u.w + u.y;
   }
-  out[blockIdx.x * blockDim.x + threadIdx.x] = acc;
+  out[blockIdx.x * blockDim.x + threadIdx.x] = acc0 + acc1 + acc2 + acc3;
 }
 
 __device__ __forceinline__ uint32_t probe_seg(float px, float py, const float4 U, float R) {
@@ -78,11 +99,12 @@ __global__ __launch_bounds__(256) void k_p2p_mix_regs(uint32_t *out, int iters, 
 
 }  // namespace
 
-// which: 0 FP32 FMA, 1 FP64 FMA, 2 LDS broadcast reads, 3 P2P test on registers.
-// Returns the achieved rate: FLOP/s (0, 1), broadcast reads per second (2) or tests
-// per second (3).
+// which: 0 FP32 FMA on VGPR operands, 1 FP64 FMA, 2 LDS broadcast 16-byte reads, 3 the
+// P2P test on register data, 4 FP32 FMA with an SGPR operand.  Returns the achieved
+// rate: FLOP/s (0, 1, 4), wave-level broadcast reads per second (2) or tests per second
+// (3).
 extern "C" gp_status gp_probe_rate(int32_t which, int32_t iters, double *rate, float *ms) {
-  if (!rate || iters <= 0 || which < 0 || which > 3)
+  if (!rate || iters <= 0 || which < 0 || which > 4)
     return set_error(GP_E_INVALID_ARG, "bad probe arguments");
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -101,8 +123,13 @@ extern "C" gp_status gp_probe_rate(int32_t which, int32_t iters, double *rate, f
     const double nthr = (double)blocks * threads;
     switch (which) {
       case 0:
-        hipLaunchKernelGGL(k_fma_f32, dim3(blocks), dim3(threads), 0, nullptr, (float *)buf, iters,
-                           0.999f, 1e-3f);
+      case 4:
+        if (which == 0)
+          hipLaunchKernelGGL(k_fma_f32<true>, dim3(blocks), dim3(threads), 0, nullptr,
+                             (float *)buf, iters, 0.999f, 1e-3f);
+        else
+          hipLaunchKernelGGL(k_fma_f32<false>, dim3(blocks), dim3(threads), 0, nullptr,
+                             (float *)buf, iters, 0.999f, 1e-3f);
         work = nthr * iters * 8 * 2;
         break;
       case 1:
