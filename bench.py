@@ -221,6 +221,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-classes", action="store_true",
+                    help="skip the PIP cell-classification measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -346,6 +348,30 @@ def main():
         probes[key] = r / 1e12 if key.endswith("tflops") else r
     probes["p2p_refine_vs_regs_probe"] = (tests_p2p / (p2p_ref / 1e3)) / probes["p2p_test_regs_tests_per_s"]
     detail["probes"] = probes
+    # PIP with cell classes (Sec. III.A): points in cells wholly inside a polygon take its
+    # id untested, cells outside are skipped; same ids, fewer tests (reported apart from
+    # the headline, which runs every candidate test)
+    if not args.no_classes:
+        from paper_1403_0802_amd import synth
+        p3c = synth.GridParams(**{**p3.__dict__, "cell_classes": 1})
+        t0 = time.perf_counter()
+        grid3c = gp.gp_build_grid("pip", geom3, p3c)
+        build_c = 1e3 * (time.perf_counter() - t0)
+        tune = gp.gp_get_tuning(grid3, prec)
+        gp.gp_set_tuning(grid3c, prec, **{k: tune[k] for k in tune})
+        id3c = torch.empty_like(id3)
+        gp.gp_pip(grid3c, x3, y3, id3c, prec, ws3, stream, False)
+        stc = [gp.gp_pip(grid3c, x3, y3, id3c, prec, ws3, stream, True) for _ in range(3)]
+        info = grid3c.info()
+        detail["pip_cell_classes"] = {
+            "ms": avg(stc, "ms_total"), "ms_refine": avg(stc, "ms_refine"),
+            "ms_without": avg(st_pip, "ms_total"), "tests": stc[0]["tests"],
+            "tests_avoided": stc[0]["tests_avoided"],
+            "ids_equal_unclassified": bool(torch.equal(id3c, id3)),
+            "pairs": {"inside": info["n_pairs_inside"], "outside": info["n_pairs_outside"],
+                      "boundary": info["n_pairs_boundary"]},
+            "grid_build_ms": build_c}
+        del grid3c, id3c
     # the FP64 form on the same inputs, for comparison
     if not args.no_fp64:
         del ws3, ws4

@@ -35,10 +35,9 @@
  *            bitwise reproducible against a scalar FP64 implementation).
  *   GP_MIXED tests in FP32 on coordinates rebased to each grid cell's centre, with a
  *            per-edge guard band; any point whose FP32 decision could differ from the
- *            FP64 one is recomputed in FP64 on the GPU.  PIP ids and P2P ids are
- *            identical to GP_FP64; a P2P distance that is not recomputed carries an
- *            absolute error of at most 16*2^-24*(|cell half-diagonal| + M), M the
- *            largest rebased vertex magnitude among the segments near the cell.
+ *            FP64 one is recomputed in FP64 on the GPU.  PIP ids, P2P ids and P2P
+ *            distances are identical to GP_FP64: the winning polylines' distances are
+ *            always evaluated in FP64, in the operation order above.
  *
  * Conventions:
  *   - All calls return a gp_status; 0 is success.  gp_last_error() returns a
@@ -97,12 +96,21 @@ typedef struct gp_geometry {
 
 /* Grid of cell size cell_size > 0.  nx == 0 or ny == 0 derives the extent from the
  * (expanded, padded) MBBs: x0 = smallest MBB corner, nx = floor((max-x0)/cs)+1.
- * radius_D >= 0 is the P2P range (ignored for PIP). */
+ * radius_D >= 0 is the P2P range (ignored for PIP).
+ * pip_cell_classes = 1 (PIP only; 0 otherwise) classifies every (cell, polygon) pair at
+ * build time (Sec. III.A): a pair whose cell, widened by max(cs*2^-20, M*2^-40) with M
+ * the largest grid coordinate magnitude, meets no edge's bounding box lies wholly
+ * inside or wholly outside the polygon, decided by the FP64 crossing parity of the cell
+ * centre; every other pair is a boundary pair.  Queries then skip outside pairs, give
+ * every still undecided point of the cell an inside pair's id without testing, and test
+ * only boundary pairs.  Results are identical to the unclassified grid; gp_stats.tests
+ * counts the tests performed and tests_avoided the candidate tests skipped. */
 typedef struct gp_grid_params {
     double cell_size;
     double radius_D;
     double x0, y0;
     int64_t nx, ny;
+    int32_t pip_cell_classes;
 } gp_grid_params;
 
 typedef struct gp_grid gp_grid;
@@ -122,12 +130,15 @@ typedef struct gp_stats {
     int64_t n_points;     /* points in the call */
     int64_t n_paired;     /* points in a cell with >= 1 candidate */
     int64_t n_items;      /* refinement work items (cell, point chunk) */
-    uint64_t tests;       /* point-edge tests: sum over cells npts * sum nedges(cands) */
+    uint64_t tests;       /* point-edge tests performed: sum over cells npts * sum nedges
+                             over the candidates refined (all of them unless the grid
+                             was built with pip_cell_classes) */
     int64_t n_rechecked;  /* GP_MIXED: points recomputed in FP64 */
     float ms_pairing;     /* hash + sort + gather + item list */
     float ms_refine;      /* refinement kernel */
     float ms_recheck;     /* FP64 recheck kernel */
     float ms_total;
+    uint64_t tests_avoided; /* candidate tests skipped by the cell classes (else 0) */
 } gp_stats;
 
 /* Build the device-resident grid for a feature set (Sec. III.A filter):
@@ -145,6 +156,7 @@ typedef struct gp_grid_info {
     int32_t kind;
     double x0, y0, cell_size, radius_D;
     int64_t nx, ny, n_features, n_edges, n_pairs;
+    int64_t n_pairs_inside, n_pairs_outside, n_pairs_boundary; /* cell classes, else 0 */
 } gp_grid_info;
 gp_status gp_grid_get_info(const gp_grid *grid, gp_grid_info *info);
 

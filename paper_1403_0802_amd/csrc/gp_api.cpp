@@ -124,6 +124,8 @@ extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
   if (!(D >= 0.0) || !std::isfinite(D))
     return set_error(GP_E_INVALID_ARG, "radius_D must be finite and >= 0");
   if (params->nx < 0 || params->ny < 0) return set_error(GP_E_INVALID_ARG, "negative nx/ny");
+  if (params->pip_cell_classes != 0 && params->pip_cell_classes != 1)
+    return set_error(GP_E_INVALID_ARG, "pip_cell_classes must be 0 or 1");
   const bool derive = params->nx == 0 || params->ny == 0;
   if (!derive && (!std::isfinite(params->x0) || !std::isfinite(params->y0)))
     return set_error(GP_E_INVALID_ARG, "non-finite grid origin");
@@ -319,8 +321,26 @@ extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
     if (npairs)
       GP_TRY_HIP_G(hipMemcpyAsync(g->d_cand_id, svals, (size_t)npairs * 4,
                                   hipMemcpyDeviceToDevice, s));
-    GP_TRY_HIP_G(launch_cell_edges(g->d_cand_off, g->d_cand_id, g->d_eoff, ncells,
-                                   g->d_cell_edges, s));
+    if (kind == GP_PIP && params->pip_cell_classes) {
+      // margin of the cell classes: the MBB pad, or more where coordinates are large
+      const double M = std::max({std::fabs(x0), std::fabs(y0), std::fabs(x0 + (double)nx * cs),
+                                 std::fabs(y0 + (double)ny * cs)});
+      const double margin = std::max(cs * 0x1p-20, M * 0x1p-40);
+      GP_TRY_HIP_G(hipMalloc(&g->d_cand_class, np));
+      GP_TRY_HIP_G(hipMalloc(&g->d_cell_edges_all, std::max<size_t>(ncells, 1) * 8));
+      GP_TRY_HIP_G(launch_classify_pairs(skeys, g->d_cand_id, (int32_t)npairs, g->d_eoff,
+                                         g->d_edge64, x0, y0, cs, g->nx, margin,
+                                         g->d_cand_class, s));
+      GP_TRY_HIP_G(launch_cell_edges(g->d_cand_off, g->d_cand_id, g->d_eoff, nullptr, ncells,
+                                     g->d_cell_edges_all, s));
+      std::vector<uint8_t> cls(npairs);
+      if (npairs)
+        GP_TRY_HIP_G(hipMemcpyAsync(cls.data(), g->d_cand_class, npairs, hipMemcpyDeviceToHost, s));
+      GP_TRY_HIP_G(hipStreamSynchronize(s));
+      for (uint8_t c : cls) g->npairs_class[c < 3 ? c : 2] += 1;
+    }
+    GP_TRY_HIP_G(launch_cell_edges(g->d_cand_off, g->d_cand_id, g->d_eoff, g->d_cand_class,
+                                   ncells, g->d_cell_edges, s));
     GP_TRY_HIP_G(hipStreamSynchronize(s));
   }
 #undef GP_TRY_HIP_G
@@ -339,6 +359,8 @@ extern "C" void gp_grid_free(gp_grid *g) {
   (void)hipFree(g->d_cand_off);
   (void)hipFree(g->d_cand_id);
   (void)hipFree(g->d_cell_edges);
+  (void)hipFree(g->d_cell_edges_all);
+  (void)hipFree(g->d_cand_class);
   delete g;
 }
 
@@ -354,6 +376,9 @@ extern "C" gp_status gp_grid_get_info(const gp_grid *g, gp_grid_info *info) {
   info->n_features = g->nf;
   info->n_edges = g->nedges;
   info->n_pairs = g->npairs;
+  info->n_pairs_outside = g->npairs_class[0];
+  info->n_pairs_inside = g->npairs_class[1];
+  info->n_pairs_boundary = g->d_cand_class ? g->npairs_class[2] : 0;
   return GP_OK;
 }
 
@@ -468,7 +493,7 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
     GP_TRY_HIP(hipEventRecord(ev[0], s));
   }
   GP_TRY_HIP(launch_fill_u32(w.counters, 0u, C_COUNT, s));
-  GP_TRY_HIP(launch_fill_u32((uint32_t *)w.tests, 0u, 2, s));
+  GP_TRY_HIP(launch_fill_u32((uint32_t *)w.tests, 0u, 4, s));
   uint32_t *skey = nullptr, *perm = nullptr;
   double2 *xy = nullptr;
   GP_TRY_HIP(pair_points(*g, n, px, py, w, s, &skey, &perm, &xy));
@@ -486,6 +511,7 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   a.frame64 = g->d_frame64;
   a.frame32 = g->d_frame32;
   a.circ = g->d_circ;
+  a.cand_class = g->d_cand_class;
   a.x0 = g->x0;
   a.y0 = g->y0;
   a.cs = g->cs;
@@ -507,7 +533,8 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   a.edge_chunk = t.edge_chunk;
 
   GP_TRY_HIP(launch_unpaired(a, n, w.counters + C_NPAIRED, s));
-  GP_TRY_HIP(launch_items(w.pt_off, g->d_cand_off, g->d_cell_edges, g->ncells,
+  GP_TRY_HIP(launch_items(w.pt_off, g->d_cand_off, g->d_cell_edges, g->d_cell_edges_all,
+                          g->ncells,
                           64 * t.points_per_lane * t.waves_per_item, w.item_cnt, w.scan_tmp,
                           w.items, w.counters, w.tests, s));
   if (stats) GP_TRY_HIP(hipEventRecord(ev[1], s));
@@ -520,10 +547,10 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
     GP_TRY_HIP(hipEventRecord(ev[3], s));
     GP_TRY_HIP(hipEventSynchronize(ev[3]));
     uint32_t cnt[C_COUNT];
-    unsigned long long tests = 0;
+    unsigned long long tests[2] = {0, 0};
     uint32_t nitems = 0;
     GP_TRY_HIP(hipMemcpy(cnt, w.counters, sizeof(cnt), hipMemcpyDeviceToHost));
-    GP_TRY_HIP(hipMemcpy(&tests, w.tests, 8, hipMemcpyDeviceToHost));
+    GP_TRY_HIP(hipMemcpy(tests, w.tests, 16, hipMemcpyDeviceToHost));
     GP_TRY_HIP(hipMemcpy(&nitems, a.n_items, 4, hipMemcpyDeviceToHost));
     float m01 = 0, m12 = 0, m23 = 0, m03 = 0;
     GP_TRY_HIP(hipEventElapsedTime(&m01, ev[0], ev[1]));
@@ -533,7 +560,8 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
     stats->n_points = n;
     stats->n_paired = cnt[C_NPAIRED];
     stats->n_items = nitems;
-    stats->tests = tests;
+    stats->tests = tests[0];
+    stats->tests_avoided = g->d_cell_edges_all ? tests[1] - tests[0] : 0;
     stats->n_rechecked = prec == GP_MIXED ? cnt[C_RQ] : 0;
     stats->ms_pairing = m01;
     stats->ms_refine = m12;

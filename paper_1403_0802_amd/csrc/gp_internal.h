@@ -38,6 +38,7 @@ struct RefineArgs {
   const double4 *frame64;    // P2P: (u.x, u.y, -m.u, -m.v) of each segment, absolute m
   const float4 *frame32;     // P2P: (u.x*scale, u.y*scale, |d|/2*scale, |d|)
   const double4 *circ;       // P2P: per block of P2P_BLOCK segments (centre x, y, radius, 0)
+  const uint8_t *cand_class; // PIP, optional: per candidate pair 0 outside, 1 inside, 2 boundary
   double x0, y0, cs;
   int32_t nx, ncells;
   double D, D2, D2_next;     // P2P: D, fl(D*D), the smallest double above fl(D*D)
@@ -72,7 +73,10 @@ struct Grid {
   double4 *d_circ;
   int32_t *d_cand_off;
   int32_t *d_cand_id;
-  int64_t *d_cell_edges;  // [ncells] sum of nedges over the cell's candidates
+  int64_t *d_cell_edges;  // [ncells] sum of nedges over the candidates a query refines
+  int64_t *d_cell_edges_all;  // [ncells] over all candidates (only with cell classes)
+  uint8_t *d_cand_class;  // [npairs] PIP cell classes, or null
+  int64_t npairs_class[3];  // outside, inside, boundary
   float p2p_scale;        // see RefineArgs
   gp_tuning tune[2];
   int num_cu;
@@ -132,8 +136,12 @@ hipError_t launch_raster_emit(const double *mbb, int32_t nf, double x0, double y
                               uint32_t *pair_fid, hipStream_t s);
 hipError_t launch_histogram(const uint32_t *keys, size_t n, uint32_t *cnt, hipStream_t s);
 hipError_t launch_cell_edges(const int32_t *cand_off, const int32_t *cand_id,
-                             const int32_t *eoff, int32_t ncells, int64_t *cell_edges,
-                             hipStream_t s);
+                             const int32_t *eoff, const uint8_t *cand_class, int32_t ncells,
+                             int64_t *cell_edges, hipStream_t s);
+hipError_t launch_classify_pairs(const uint32_t *pair_cell, const int32_t *cand_id,
+                                 int32_t npairs, const int32_t *eoff, const double4 *edge64,
+                                 double x0, double y0, double cs, int32_t nx, double margin,
+                                 uint8_t *cand_class, hipStream_t s);
 
 // query pipeline
 hipError_t launch_hash(const double *px, const double *py, int64_t n, double x0, double y0,
@@ -142,7 +150,8 @@ hipError_t launch_offsets(const uint32_t *skey, int64_t n, int32_t ncells, int32
                           hipStream_t s);
 hipError_t launch_unpaired(const RefineArgs &a, int64_t n, uint32_t *n_paired, hipStream_t s);
 hipError_t launch_items(const int32_t *pt_off, const int32_t *cand_off,
-                        const int64_t *cell_edges, int32_t ncells, int32_t chunk,
+                        const int64_t *cell_edges, const int64_t *cell_edges_all,
+                        int32_t ncells, int32_t chunk,
                         uint32_t *item_cnt, uint32_t *scan_tmp, Item *items, uint32_t *counters,
                         unsigned long long *tests, hipStream_t s);
 hipError_t launch_refine(gp_kind kind, gp_precision prec, const RefineArgs &a,

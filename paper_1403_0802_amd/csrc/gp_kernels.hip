@@ -548,12 +548,26 @@ hipError_t launch_histogram(const uint32_t *keys, size_t n, uint32_t *cnt, hipSt
   return hipGetLastError();
 }
 
+// Crossing of the +x ray from p with edge (lo, hi): half-open in y, strictly right.
+__device__ __forceinline__ bool cross64(double px, double py, double lox, double loy, double w,
+                                        double hiy, double h) {
+  bool st = (loy <= py) & (py < hiy);
+  double lhs = (px - lox) * h;
+  double rhs = w * (py - loy);
+  return st & (lhs < rhs);
+}
+
+// Edges a query tests per point of each cell: all candidates' edges, or with cell
+// classes only the boundary pairs' edges up to the first inside pair (which decides
+// every point still undecided, so the refinement stops there).
 __global__ void k_cell_edges(const int32_t *cand_off, const int32_t *cand_id, const int32_t *eoff,
-                             int32_t ncells, int64_t *cell_edges) {
+                             const uint8_t *cls, int32_t ncells, int64_t *cell_edges) {
   for (int32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncells;
        c += gridDim.x * blockDim.x) {
     int64_t e = 0;
     for (int32_t k = cand_off[c]; k < cand_off[c + 1]; ++k) {
+      if (cls && cls[k] == 1) break;
+      if (cls && cls[k] == 0) continue;
       int32_t f = cand_id[k];
       e += (int64_t)(eoff[f + 1] - eoff[f]);
     }
@@ -561,11 +575,61 @@ __global__ void k_cell_edges(const int32_t *cand_off, const int32_t *cand_id, co
   }
 }
 
+// Cell classes of PIP candidate pairs (Sec. III.A), one wavefront per pair.  Boundary
+// (2) when any edge's bounding box meets the cell widened by `margin`; else the cell
+// lies wholly inside (1) or outside (0) the polygon, and the FP64 crossing parity of its
+// centre says which: with every edge at least `margin` from the cell, each crossing
+// predicate is exact for every point of the cell, so all of them share the centre's
+// parity.
+__global__ void k_classify_pairs(const uint32_t *pair_cell, const int32_t *cand_id,
+                                 int32_t npairs, const int32_t *eoff, const double4 *edge64,
+                                 double x0, double y0, double cs, int32_t nx, double margin,
+                                 uint8_t *cls) {
+  const uint32_t lane = lane_id();
+  const int32_t nw = (int32_t)(gridDim.x * (blockDim.x / GP_WAVE));
+  for (int32_t p = (int32_t)(blockIdx.x * (blockDim.x / GP_WAVE) + threadIdx.x / GP_WAVE);
+       p < npairs; p += nw) {
+    const uint32_t c = pair_cell[p];
+    const int32_t f = cand_id[p];
+    const double bx0 = x0 + (double)(c % (uint32_t)nx) * cs;
+    const double by0 = y0 + (double)(c / (uint32_t)nx) * cs;
+    const double bx1 = bx0 + cs, by1 = by0 + cs;
+    const double qx = bx0 + 0.5 * cs, qy = by0 + 0.5 * cs;
+    bool touch = false;
+    uint64_t par = 0;
+    const int32_t e1 = eoff[f + 1];
+    for (int32_t e = eoff[f] + (int32_t)lane; e - (int32_t)lane < e1; e += GP_WAVE) {
+      bool cr = false;
+      if (e < e1) {
+        const double4 r = edge64[e];  // (lo.x, lo.y, hi.x, hi.y)
+        const double mnx = fmin(r.x, r.z), mxx = fmax(r.x, r.z);
+        touch |= !(mxx < bx0 - margin || mnx > bx1 + margin || r.w < by0 - margin ||
+                   r.y > by1 + margin);
+        cr = cross64(qx, qy, r.x, r.y, r.z - r.x, r.w, r.w - r.y);
+      }
+      par ^= ballot(cr);
+    }
+    const bool bd = ballot(touch) != 0;
+    if (lane == 0) cls[p] = bd ? 2 : (__popcll(par) & 1 ? 1 : 0);
+  }
+}
+
+hipError_t launch_classify_pairs(const uint32_t *pair_cell, const int32_t *cand_id,
+                                 int32_t npairs, const int32_t *eoff, const double4 *edge64,
+                                 double x0, double y0, double cs, int32_t nx, double margin,
+                                 uint8_t *cand_class, hipStream_t s) {
+  if (npairs <= 0) return hipSuccess;
+  const unsigned g = grid_for((size_t)npairs * GP_WAVE, 256, 8192);
+  hipLaunchKernelGGL(k_classify_pairs, dim3(g), dim3(256), 0, s, pair_cell, cand_id, npairs,
+                     eoff, edge64, x0, y0, cs, nx, margin, cand_class);
+  return hipGetLastError();
+}
+
 hipError_t launch_cell_edges(const int32_t *cand_off, const int32_t *cand_id,
-                             const int32_t *eoff, int32_t ncells, int64_t *cell_edges,
-                             hipStream_t s) {
+                             const int32_t *eoff, const uint8_t *cand_class, int32_t ncells,
+                             int64_t *cell_edges, hipStream_t s) {
   hipLaunchKernelGGL(k_cell_edges, dim3(grid_for(ncells, 256, 8192)), dim3(256), 0, s, cand_off,
-                     cand_id, eoff, ncells, cell_edges);
+                     cand_id, eoff, cand_class, ncells, cell_edges);
   return hipGetLastError();
 }
 
@@ -652,26 +716,34 @@ hipError_t launch_unpaired(const RefineArgs &a, int64_t n, uint32_t *n_paired, h
   return hipGetLastError();
 }
 
+// Items per cell, and the test counts: tests[0] over the candidates a query refines,
+// tests[1] over all candidates (only when cell_edges_all is given, i.e. cell classes).
 __global__ void k_item_count(const int32_t *pt_off, const int32_t *cand_off,
-                             const int64_t *cell_edges, int32_t ncells, int32_t chunk,
-                             uint32_t *cnt, unsigned long long *tests) {
+                             const int64_t *cell_edges, const int64_t *cell_edges_all,
+                             int32_t ncells, int32_t chunk, uint32_t *cnt,
+                             unsigned long long *tests) {
   // the loop bound is uniform per block so that every lane joins the wave reduction
   for (int32_t c0 = blockIdx.x * blockDim.x; c0 <= ncells; c0 += gridDim.x * blockDim.x) {
     const int32_t c = c0 + (int32_t)threadIdx.x;
     uint32_t q = 0;
-    unsigned long long t = 0;
+    unsigned long long t = 0, ta = 0;
     if (c < ncells) {
       int32_t np = pt_off[c + 1] - pt_off[c];
       int32_t nc = cand_off[c + 1] - cand_off[c];
       if (np > 0 && nc > 0) {
         q = (uint32_t)((np + chunk - 1) / chunk);
         t = (unsigned long long)np * (unsigned long long)cell_edges[c];
+        if (cell_edges_all) ta = (unsigned long long)np * (unsigned long long)cell_edges_all[c];
       }
     }
     if (c <= ncells) cnt[c] = q;
-    // wavefront reduction of the test count, one atomic per wave
-    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, GP_WAVE);
+    // wavefront reductions of the test counts, one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) {
+      t += __shfl_xor(t, off, GP_WAVE);
+      ta += __shfl_xor(ta, off, GP_WAVE);
+    }
     if (lane_id() == 0 && t) atomicAdd(tests, t);
+    if (lane_id() == 0 && ta) atomicAdd(tests + 1, ta);
   }
 }
 
@@ -690,13 +762,14 @@ __global__ void k_item_emit(const int32_t *pt_off, int32_t ncells, int32_t chunk
 }
 
 hipError_t launch_items(const int32_t *pt_off, const int32_t *cand_off,
-                        const int64_t *cell_edges, int32_t ncells, int32_t chunk,
+                        const int64_t *cell_edges, const int64_t *cell_edges_all,
+                        int32_t ncells, int32_t chunk,
                         uint32_t *item_cnt, uint32_t *scan_tmp, Item *items, uint32_t *counters,
                         unsigned long long *tests, hipStream_t s) {
   (void)counters;
   unsigned g = grid_for((size_t)ncells + 1, 256, 8192);
   hipLaunchKernelGGL(k_item_count, dim3(g), dim3(256), 0, s, pt_off, cand_off, cell_edges,
-                     ncells, chunk, item_cnt, tests);
+                     cell_edges_all, ncells, chunk, item_cnt, tests);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = launch_exclusive_scan_u32(item_cnt, item_cnt, (size_t)ncells + 1, scan_tmp, s);
@@ -722,14 +795,6 @@ hipError_t launch_copy_perm(const uint32_t *perm, int64_t n, int32_t *out, hipSt
 // The two refinement predicates in plain FP64, in the operation order of the
 // definitions (Sec. III.C crossing, Sec. III.B / Fig. 2 segment distance).
 
-// Crossing of the +x ray from p with edge (lo, hi): half-open in y, strictly right.
-__device__ __forceinline__ bool cross64(double px, double py, double lox, double loy, double w,
-                                        double hiy, double h) {
-  bool st = (loy <= py) & (py < hiy);
-  double lhs = (px - lox) * h;
-  double rhs = w * (py - loy);
-  return st & (lhs < rhs);
-}
 
 // Squared distance from p to segment (a, b): endpoint a when t <= 0, endpoint b when
 // t >= L2, else the perpendicular foot.
@@ -813,6 +878,14 @@ __device__ void pip64_item(const RefineArgs &a, const Item it, PipRec64 *lds) {
   const int32_t k0 = a.cand_off[it.cell], k1 = a.cand_off[it.cell + 1];
   for (int32_t k = k0; k < k1; ++k) {
     const int32_t f = a.cand_id[k];
+    const int cls = a.cand_class ? a.cand_class[k] : 2;
+    if (cls == 0) continue;  // the cell lies outside polygon f
+    if (cls == 1) {          // inside: every undecided point takes f, and all are decided
+#pragma unroll
+      for (int j = 0; j < PPL; ++j)
+        if (best[j] < 0) best[j] = f;
+      break;
+    }
     const int32_t e0 = a.eoff[f], e1 = a.eoff[f + 1];
     uint64_t par[PPL];
 #pragma unroll
@@ -892,6 +965,14 @@ __device__ void pipmix_item(const RefineArgs &a, const Item it, float4 *ldsA, fl
   const int32_t k0 = a.cand_off[it.cell], k1 = a.cand_off[it.cell + 1];
   for (int32_t k = k0; k < k1; ++k) {
     const int32_t f = a.cand_id[k];
+    const int cls = a.cand_class ? a.cand_class[k] : 2;
+    if (cls == 0) continue;  // the cell lies outside polygon f
+    if (cls == 1) {          // inside: every undecided point takes f, and all are decided
+#pragma unroll
+      for (int j = 0; j < PPL; ++j)
+        if (best[j] < 0 && !rq[j]) best[j] = f;
+      break;
+    }
     const int32_t e0 = a.eoff[f], e1 = a.eoff[f + 1];
     uint64_t par[PPL], flg[PPL];
 #pragma unroll

@@ -45,7 +45,8 @@ class gp_geometry(Structure):
 
 class gp_grid_params(Structure):
     _fields_ = [("cell_size", c_double), ("radius_D", c_double), ("x0", c_double),
-                ("y0", c_double), ("nx", c_int64), ("ny", c_int64)]
+                ("y0", c_double), ("nx", c_int64), ("ny", c_int64),
+                ("pip_cell_classes", c_int32)]
 
 
 class gp_tuning(Structure):
@@ -59,7 +60,8 @@ class gp_tuning(Structure):
 class gp_stats(Structure):
     _fields_ = [("n_points", c_int64), ("n_paired", c_int64), ("n_items", c_int64),
                 ("tests", c_uint64), ("n_rechecked", c_int64), ("ms_pairing", c_float),
-                ("ms_refine", c_float), ("ms_recheck", c_float), ("ms_total", c_float)]
+                ("ms_refine", c_float), ("ms_recheck", c_float), ("ms_total", c_float),
+                ("tests_avoided", c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -68,7 +70,8 @@ class gp_stats(Structure):
 class gp_grid_info(Structure):
     _fields_ = [("kind", c_int32), ("x0", c_double), ("y0", c_double), ("cell_size", c_double),
                 ("radius_D", c_double), ("nx", c_int64), ("ny", c_int64), ("n_features", c_int64),
-                ("n_edges", c_int64), ("n_pairs", c_int64)]
+                ("n_edges", c_int64), ("n_pairs", c_int64), ("n_pairs_inside", c_int64),
+                ("n_pairs_outside", c_int64), ("n_pairs_boundary", c_int64)]
 
 
 class gp_serve_opts(Structure):
@@ -196,7 +199,8 @@ class Grid:
 def gp_build_grid(kind, geom, params, stream=None) -> Grid:
     """``kind`` is "pip"/"p2p" (or GP_PIP/GP_P2P); ``geom`` has numpy ``ring_vert_off``,
     ``x``, ``y`` and ``feature_ring_off`` (None for polylines); ``params`` has
-    ``cell_size, radius_D, x0, y0, nx, ny``."""
+    ``cell_size, radius_D, x0, y0, nx, ny`` and optionally ``cell_classes`` (PIP: 1
+    classifies every cell/polygon pair at build time)."""
     k = KINDS.get(kind, kind)
     rvo = np.ascontiguousarray(geom.ring_vert_off, dtype=np.int64)
     fro = (None if geom.feature_ring_off is None
@@ -206,7 +210,8 @@ def gp_build_grid(kind, geom, params, stream=None) -> Grid:
     nf = len(rvo) - 1 if fro is None else len(fro) - 1
     g = gp_geometry(nf, _ptr(fro), len(rvo) - 1, _ptr(rvo), len(x), _ptr(x), _ptr(y), 0)
     p = gp_grid_params(float(params.cell_size), float(getattr(params, "radius_D", 0.0)),
-                       float(params.x0), float(params.y0), int(params.nx), int(params.ny))
+                       float(params.x0), float(params.y0), int(params.nx), int(params.ny),
+                       int(getattr(params, "cell_classes", 0)))
     h = c_void_p()
     check(lib.gp_build_grid(k, ctypes.byref(g), ctypes.byref(p), _stream(stream),
                             ctypes.byref(h)))

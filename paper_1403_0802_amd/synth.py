@@ -63,6 +63,7 @@ class GridParams:
     y0: float = 0.0
     nx: int = 0  # 0: derive the extent from the (expanded) MBBs
     ny: int = 0
+    cell_classes: int = 0  # PIP: 1 asks the GPU grid to classify cell/polygon pairs
 
 
 @dataclasses.dataclass

@@ -265,6 +265,75 @@ def test_holes_overlaps_and_long_rings(gp):
         assert np.array_equal(got, want), (prec, np.sum(got != want))
 
 
+# ---------------------------------------------------------------- PIP cell classes
+
+
+def test_pip_cell_classes_counts_and_ids(gp):
+    """An axis-aligned square on cell lines: the classes are known exactly (30x30
+    inside cells, a two-cell boundary ring, nothing outside), and the ids equal the
+    oracle's with and without the classes."""
+    say("pip cell classes: square")
+    g = pins.polygons([[pins.box(0.25, 0.25, 0.75, 0.75)]])
+    rng = np.random.default_rng(12)
+    px, py = rng.uniform(0, 1, (2, 100_000))
+    px = np.concatenate([px, [0.25, 0.75, 0.5, 0.25 - 1e-17, 0.75 - 1e-17]])
+    py = np.concatenate([py, [0.5, 0.5, 0.25, 0.25, 0.75 - 1e-17]])
+    params = synth.GridParams(cell_size=1 / 64, nx=64, ny=64, cell_classes=1)
+    want = oracle.pip(g, px, py)
+    grid = gp.gp_build_grid("pip", g, params)
+    info = grid.info()
+    assert (info["n_pairs"], info["n_pairs_inside"], info["n_pairs_boundary"],
+            info["n_pairs_outside"]) == (34 * 34, 30 * 30, 34 * 34 - 30 * 30, 0), info
+    for prec in ("fp64", "mixed"):
+        got, st = run_gpu(gp, grid, px, py, prec, stats=True)
+        assert np.array_equal(got, want), (prec, np.sum(got != want))
+        assert st["tests_avoided"] > 0 and st["tests"] > 0
+
+
+@pytest.mark.parametrize("case", ["c1", "holes", "c3"])
+def test_pip_cell_classes_equal_unclassified(gp, c1, c3_geom, case):
+    """Classified grids give the oracle's ids bit for bit in both forms, and perform
+    exactly the candidate tests minus the avoided ones."""
+    say("pip cell classes", case)
+    rng = np.random.default_rng(13)
+    if case == "c1":
+        w, want = c1
+        g, params, px, py = w.geom, w.params, w.px, w.py
+    elif case == "holes":
+        t = np.sort(rng.uniform(0, 2 * np.pi, 5000))
+        big = list(zip(0.5 + 0.45 * np.cos(t), 0.5 + 0.45 * np.sin(t)))
+        sq = pins.box(0.2, 0.2, 0.8, 0.8)
+        hole = pins.box(0.3, 0.3, 0.7, 0.7, ccw=False)
+        dup = pins.box(0.1, 0.6, 0.4, 0.9) + [(0.1, 0.6)]
+        g = pins.polygons([[sq, hole], [big], [dup]])
+        params = synth.GridParams(cell_size=1 / 32, nx=32, ny=32)
+        px, py = rng.uniform(0, 1, (2, 200_000))
+        want = oracle.pip(g, px, py, oracle.build_grid(g, params))
+    else:
+        g, _ = c3_geom
+        params = synth.GridParams(cell_size=1 / 1024, nx=1024, ny=1024)
+        px, py = synth.config3_points(2_000_000, seed_salt=3)
+        want = None
+    plain = gp.gp_build_grid("pip", g, params)
+    cparams = synth.GridParams(**{**params.__dict__, "cell_classes": 1})
+    classed = gp.gp_build_grid("pip", g, cparams)
+    info = classed.info()
+    assert info["n_pairs_inside"] + info["n_pairs_outside"] + info["n_pairs_boundary"] == info["n_pairs"]
+    for prec in ("fp64", "mixed"):
+        ref, st0 = run_gpu(gp, plain, px, py, prec, stats=True)
+        got, st1 = run_gpu(gp, classed, px, py, prec, stats=True)
+        assert np.array_equal(got, ref), (case, prec, np.sum(got != ref))
+        if want is not None:
+            assert np.array_equal(got, want), (case, prec)
+        assert st0["tests_avoided"] == 0
+        assert st1["tests"] + st1["tests_avoided"] == st0["tests"]
+        say("  ", prec, "tests", st1["tests"], "avoided", st1["tests_avoided"], "classes", info)
+    if case == "c3":
+        sel = rng.choice(len(px), 20_000, replace=False)
+        want = oracle.pip(g, px[sel], py[sel], oracle.build_grid(g, params))
+        assert np.array_equal(got[sel], want)
+
+
 def test_near_edge_sweep_mixed(gp):
     """Points at distances 1e-15 .. 1e-3 (relative to the unit square) from polygon
     edges, on both sides: the guard band must send every doubtful one to FP64."""
