@@ -209,6 +209,24 @@ def serving_run(gp, torch, grid3, grid4, n_requests: int, precision: str):
             "slots": slots, "slot_points": slot_points}
 
 
+def cell_sweep(gp, torch, dev, c3, c4):
+    """The filter-versus-refine trade-off (Sec. III.A): query time, candidate pairs, tests
+    and grid memory at five cell sizes around each configuration's default, on the full
+    point sets, mixed form, default kernel tuning."""
+    out = {}
+    for name, kind, (geom, p, px, py), sizes in (
+            ("pip_c3", "pip", c3, [1 / 256, 1 / 512, 1 / 1024, 1 / 2048, 1 / 4096]),
+            ("p2p_c4", "p2p", c4, [25.0, 50.0, 100.0, 200.0, 400.0])):
+        x, y = torch.from_numpy(px).to(dev), torch.from_numpy(py).to(dev)
+        t0 = time.perf_counter()
+        best, rows = gp.gp_sweep_cell_size(kind, geom, p, sizes, x, y, "mixed")
+        log(f"[bench] {name} sweep {time.perf_counter() - t0:.1f}s best {best}")
+        out[name] = {"default_cell_size": p.cell_size, "best_cell_size": best, "rows": rows}
+        del x, y
+        torch.cuda.empty_cache()
+    print(json.dumps({"cell_sweep": out, "workload": WORKLOAD_NAME}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,6 +243,9 @@ def main():
                     help="skip the PIP cell-classification measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--cell-sweep", action="store_true",
+                    help="instead of the step: sweep the cell size of both grids on the full "
+                         "workloads (gp_sweep_cell_size) and print one JSON line")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter "
                          "CSVs of a --copy-probe run, then exit")
@@ -247,6 +268,9 @@ def main():
     c3, c4 = build_workloads(args.scale)
     geom3, p3, px3, py3 = c3
     geom4, p4, px4, py4 = c4
+    if args.cell_sweep:
+        cell_sweep(gp, torch, dev, c3, c4)
+        return
     t0 = time.perf_counter()
     grid3 = gp.gp_build_grid("pip", geom3, p3)
     t1 = time.perf_counter()

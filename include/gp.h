@@ -157,6 +157,7 @@ typedef struct gp_grid_info {
     double x0, y0, cell_size, radius_D;
     int64_t nx, ny, n_features, n_edges, n_pairs;
     int64_t n_pairs_inside, n_pairs_outside, n_pairs_boundary; /* cell classes, else 0 */
+    int64_t device_bytes;  /* device memory the grid holds */
 } gp_grid_info;
 gp_status gp_grid_get_info(const gp_grid *grid, gp_grid_info *info);
 
@@ -197,6 +198,22 @@ gp_status gp_get_tuning(const gp_grid *grid, gp_precision prec, gp_tuning *tunin
 gp_status gp_autotune(gp_grid *grid, gp_precision prec, int64_t n, const double *px,
                       const double *py, void *ws, size_t ws_bytes, void *hip_stream,
                       gp_tuning *best, float *best_ms);
+
+/* Cell-size sweep: the filter-versus-refine trade-off that Sec. III.A leaves open (a
+ * finer grid pairs fewer features with each point but costs more pairs and memory).
+ * For each of the n_sizes cell sizes, builds the grid of *params with that cell size
+ * (a derived extent is re-derived; an explicit one keeps x0, y0 and covers the same
+ * area: nx = ceil(nx0 * cs0 / cs)), runs the query on the n sample points (device
+ * pointers) once to warm up and three times timed, and frees the grid again.  Per size
+ * i: ms_query[i] the median gp_stats.ms_total (NAN when that grid exceeds the library's
+ * limits), n_pairs[i] the candidate pairs, tests[i] the tests performed, grid_bytes[i]
+ * the grid's device memory.  *best receives the fastest size.  Any per-size output may
+ * be NULL.  Results never depend on the cell size.  Allocates; synchronous. */
+gp_status gp_sweep_cell_size(gp_kind kind, const gp_geometry *geom, const gp_grid_params *params,
+                             const double *cell_sizes, int32_t n_sizes, int64_t n,
+                             const double *px, const double *py, gp_precision prec,
+                             void *hip_stream, double *best, float *ms_query,
+                             int64_t *n_pairs, uint64_t *tests, int64_t *grid_bytes);
 
 /* Measurement probe (not part of the join): sustained rate on the current device of
  * which = 0: FP32 FMA with every operand in a VGPR (FLOP/s), 1: FP64 FMA (FLOP/s),

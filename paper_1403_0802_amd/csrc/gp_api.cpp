@@ -364,6 +364,16 @@ extern "C" void gp_grid_free(gp_grid *g) {
   delete g;
 }
 
+// Device bytes held by a grid (the allocations of gp_build_grid).
+static int64_t grid_device_bytes(const Grid &g) {
+  const int64_t ne = std::max<int64_t>(g.nedges, 1), nc = std::max<int64_t>(g.ncells, 1);
+  const int64_t np = std::max<int64_t>(g.npairs, 1);
+  int64_t b = ((int64_t)g.nf + 1) * 4 + ne * (32 + 4) + (nc + 1) * 4 + np * 4 + nc * 8;
+  if (g.kind == GP_P2P) b += ne * (32 + 16) + (ne + P2P_BLOCK - 1) / P2P_BLOCK * 32;
+  if (g.d_cand_class) b += np + nc * 8;
+  return b;
+}
+
 extern "C" gp_status gp_grid_get_info(const gp_grid *g, gp_grid_info *info) {
   if (!g || !info) return set_error(GP_E_INVALID_ARG, "null argument");
   info->kind = g->kind;
@@ -379,6 +389,7 @@ extern "C" gp_status gp_grid_get_info(const gp_grid *g, gp_grid_info *info) {
   info->n_pairs_outside = g->npairs_class[0];
   info->n_pairs_inside = g->npairs_class[1];
   info->n_pairs_boundary = g->d_cand_class ? g->npairs_class[2] : 0;
+  info->device_bytes = grid_device_bytes(*g);
   return GP_OK;
 }
 
@@ -683,5 +694,68 @@ extern "C" gp_status gp_autotune(gp_grid *g, gp_precision prec, int64_t n, const
   g->tune[prec] = best_cfg;
   if (best) *best = best_cfg;
   if (best_ms) *best_ms = best_t;
+  return GP_OK;
+}
+
+extern "C" gp_status gp_sweep_cell_size(gp_kind kind, const gp_geometry *geom,
+                                        const gp_grid_params *params, const double *cell_sizes,
+                                        int32_t n_sizes, int64_t n, const double *px,
+                                        const double *py, gp_precision prec, void *hip_stream,
+                                        double *best, float *ms_query, int64_t *n_pairs,
+                                        uint64_t *tests, int64_t *grid_bytes) {
+  if (!geom || !params || !cell_sizes || n_sizes <= 0 || n <= 0 || !px || !py)
+    return set_error(GP_E_INVALID_ARG, "bad sweep arguments");
+  if (prec != GP_FP64 && prec != GP_MIXED) return set_error(GP_E_INVALID_ARG, "bad precision");
+  for (int32_t i = 0; i < n_sizes; ++i)
+    if (!(cell_sizes[i] > 0.0) || !std::isfinite(cell_sizes[i]))
+      return set_error(GP_E_INVALID_ARG, "cell sizes must be finite and > 0");
+  hipStream_t s = (hipStream_t)hip_stream;
+  DevBuf d_id, d_dist;
+  GP_TRY_HIP(d_id.alloc((size_t)n * 4));
+  GP_TRY_HIP(d_dist.alloc((size_t)n * 8));
+  const bool derive = params->nx == 0 || params->ny == 0;
+  double best_cs = NAN;
+  float best_t = INFINITY;
+  for (int32_t i = 0; i < n_sizes; ++i) {
+    gp_grid_params p = *params;
+    p.cell_size = cell_sizes[i];
+    if (!derive) {
+      p.nx = (int64_t)std::ceil((double)params->nx * params->cell_size / p.cell_size);
+      p.ny = (int64_t)std::ceil((double)params->ny * params->cell_size / p.cell_size);
+    }
+    if (ms_query) ms_query[i] = NAN;
+    if (n_pairs) n_pairs[i] = -1;
+    if (tests) tests[i] = 0;
+    if (grid_bytes) grid_bytes[i] = -1;
+    gp_grid *g = nullptr;
+    gp_status rc = gp_build_grid(kind, geom, &p, hip_stream, &g);
+    if (rc == GP_E_CAPACITY) continue;  // this size exceeds the limits: skipped
+    if (rc) return rc;
+    size_t wsb = 0;
+    rc = gp_workspace_bytes(g, n, prec, &wsb);
+    DevBuf ws;
+    if (!rc && ws.alloc(wsb) != hipSuccess) rc = set_error(GP_E_OOM, "sweep workspace");
+    float times[3] = {0, 0, 0};
+    gp_stats st;
+    for (int r = 0; r < 4 && !rc; ++r) {
+      rc = run_query(g, kind, n, px, py, d_id.as<int32_t>(), d_dist.as<double>(), prec, ws.p,
+                     wsb, s, &st, nullptr);
+      if (r > 0) times[r - 1] = st.ms_total;
+    }
+    if (!rc) {
+      std::sort(times, times + 3);
+      if (ms_query) ms_query[i] = times[1];
+      if (n_pairs) n_pairs[i] = g->npairs;
+      if (tests) tests[i] = st.tests;
+      if (grid_bytes) grid_bytes[i] = grid_device_bytes(*g);
+      if (times[1] < best_t) {
+        best_t = times[1];
+        best_cs = cell_sizes[i];
+      }
+    }
+    gp_grid_free(g);
+    if (rc) return rc;
+  }
+  if (best) *best = best_cs;
   return GP_OK;
 }

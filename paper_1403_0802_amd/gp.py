@@ -71,7 +71,8 @@ class gp_grid_info(Structure):
     _fields_ = [("kind", c_int32), ("x0", c_double), ("y0", c_double), ("cell_size", c_double),
                 ("radius_D", c_double), ("nx", c_int64), ("ny", c_int64), ("n_features", c_int64),
                 ("n_edges", c_int64), ("n_pairs", c_int64), ("n_pairs_inside", c_int64),
-                ("n_pairs_outside", c_int64), ("n_pairs_boundary", c_int64)]
+                ("n_pairs_outside", c_int64), ("n_pairs_boundary", c_int64),
+                ("device_bytes", c_int64)]
 
 
 class gp_serve_opts(Structure):
@@ -110,6 +111,8 @@ _SIGS = {
     "gp_autotune": ([_P, c_int32, c_int64, _P, _P, _P, ctypes.c_size_t, _P, POINTER(gp_tuning),
                      POINTER(c_float)], c_int32),
     "gp_probe_rate": ([c_int32, c_int32, POINTER(c_double), POINTER(c_float)], c_int32),
+    "gp_sweep_cell_size": ([c_int32, _P, _P, _P, c_int32, c_int64, _P, _P, c_int32, _P,
+                            POINTER(c_double), _P, _P, _P, _P], c_int32),
     "gp_serve_create": ([_P, _P, POINTER(gp_serve_opts), POINTER(_P)], c_int32),
     "gp_serve_submit": ([_P, c_int32, c_int64, _P, _P, _P, _P, POINTER(c_uint64)], c_int32),
     "gp_serve_poll": ([_P, c_uint64, POINTER(c_int32)], c_int32),
@@ -202,16 +205,8 @@ def gp_build_grid(kind, geom, params, stream=None) -> Grid:
     ``cell_size, radius_D, x0, y0, nx, ny`` and optionally ``cell_classes`` (PIP: 1
     classifies every cell/polygon pair at build time)."""
     k = KINDS.get(kind, kind)
-    rvo = np.ascontiguousarray(geom.ring_vert_off, dtype=np.int64)
-    fro = (None if geom.feature_ring_off is None
-           else np.ascontiguousarray(geom.feature_ring_off, dtype=np.int64))
-    x = np.ascontiguousarray(geom.x, dtype=np.float64)
-    y = np.ascontiguousarray(geom.y, dtype=np.float64)
-    nf = len(rvo) - 1 if fro is None else len(fro) - 1
-    g = gp_geometry(nf, _ptr(fro), len(rvo) - 1, _ptr(rvo), len(x), _ptr(x), _ptr(y), 0)
-    p = gp_grid_params(float(params.cell_size), float(getattr(params, "radius_D", 0.0)),
-                       float(params.x0), float(params.y0), int(params.nx), int(params.ny),
-                       int(getattr(params, "cell_classes", 0)))
+    g, keep = _geometry(geom)
+    p = _params(params)
     h = c_void_p()
     check(lib.gp_build_grid(k, ctypes.byref(g), ctypes.byref(p), _stream(stream),
                             ctypes.byref(h)))
@@ -287,6 +282,46 @@ def run(grid: Grid, px, py, prec="fp64", ws=None, stream=None, stats=False):
     out_d = torch.empty(n, dtype=torch.float64, device=px.device)
     st = gp_p2p(grid, px, py, out_id, out_d, prec, ws, stream, stats)
     return (out_id, out_d, st) if stats else (out_id, out_d)
+
+
+def _geometry(geom):
+    """numpy geometry -> (gp_geometry, arrays it points into)."""
+    rvo = np.ascontiguousarray(geom.ring_vert_off, dtype=np.int64)
+    fro = (None if geom.feature_ring_off is None
+           else np.ascontiguousarray(geom.feature_ring_off, dtype=np.int64))
+    x = np.ascontiguousarray(geom.x, dtype=np.float64)
+    y = np.ascontiguousarray(geom.y, dtype=np.float64)
+    nf = len(rvo) - 1 if fro is None else len(fro) - 1
+    g = gp_geometry(nf, _ptr(fro), len(rvo) - 1, _ptr(rvo), len(x), _ptr(x), _ptr(y), 0)
+    return g, (rvo, fro, x, y)
+
+
+def _params(params):
+    return gp_grid_params(float(params.cell_size), float(getattr(params, "radius_D", 0.0)),
+                          float(params.x0), float(params.y0), int(params.nx), int(params.ny),
+                          int(getattr(params, "cell_classes", 0)))
+
+
+def gp_sweep_cell_size(kind, geom, params, cell_sizes, px, py, prec="mixed", stream=None):
+    """Times the query on device points ``px, py`` for each cell size; returns
+    ``(best, rows)`` with one dict per size (ms, pairs, tests, grid bytes)."""
+    k = KINDS.get(kind, kind)
+    g, keep = _geometry(geom)
+    p = _params(params)
+    cs = np.ascontiguousarray(cell_sizes, dtype=np.float64)
+    m = len(cs)
+    ms = np.zeros(m, dtype=np.float32)
+    pairs = np.zeros(m, dtype=np.int64)
+    tests = np.zeros(m, dtype=np.uint64)
+    gbytes = np.zeros(m, dtype=np.int64)
+    best = c_double()
+    check(lib.gp_sweep_cell_size(k, ctypes.byref(g), ctypes.byref(p), _ptr(cs), m, px.numel(),
+                                 _ptr(px), _ptr(py), PRECISIONS.get(prec, prec), _stream(stream),
+                                 ctypes.byref(best), _ptr(ms), _ptr(pairs), _ptr(tests),
+                                 _ptr(gbytes)))
+    rows = [{"cell_size": float(cs[i]), "ms": float(ms[i]), "pairs": int(pairs[i]),
+             "tests": int(tests[i]), "grid_bytes": int(gbytes[i])} for i in range(m)]
+    return best.value, rows
 
 
 def gp_probe_rate(which: int, iters: int):

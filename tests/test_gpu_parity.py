@@ -334,6 +334,51 @@ def test_pip_cell_classes_equal_unclassified(gp, c1, c3_geom, case):
         assert np.array_equal(got[sel], want)
 
 
+# ---------------------------------------------------------------- cell size
+
+
+@pytest.mark.parametrize("kind", ["pip", "p2p"])
+def test_results_invariant_under_cell_size(gp, c1, kind):
+    """The grid only prunes candidates that cannot matter, so ids (and distances) are the
+    same bits at every cell size, derived extent included; the sweep entry point reports
+    each size and picks one of them, with tests non-decreasing as nested cells double."""
+    say("cell-size invariance", kind)
+    if kind == "pip":
+        w, want = c1
+        g, px, py = w.geom, w.px, w.py
+        sizes = [1 / 16, 1 / 32, 1 / 64, 1 / 128]
+        base = synth.GridParams(cell_size=1 / 64, nx=64, ny=64)
+        want_d = None
+    else:
+        w = synth.config2(n_points=200_000, n_lines=5_000, seed_salt=2)
+        g, px, py = w.geom, w.px, w.py
+        sizes = [25.0, 50.0, 100.0, 200.0, 400.0]
+        base = w.params
+        want, want_d = oracle.p2p(g, px, py, base.radius_D, oracle.build_grid(g, base))
+    for prec in ("fp64", "mixed"):
+        for cs in sizes + ["derived"]:
+            if cs == "derived":
+                params = synth.GridParams(cell_size=sizes[1], radius_D=base.radius_D)
+            else:
+                f = base.cell_size / cs
+                params = synth.GridParams(cell_size=cs, radius_D=base.radius_D,
+                                          nx=int(np.ceil(base.nx * f)), ny=int(np.ceil(base.ny * f)))
+            grid = gp.gp_build_grid(kind, g, params)
+            r = run_gpu(gp, grid, px, py, prec)
+            if kind == "pip":
+                assert np.array_equal(r, want), (prec, cs, np.sum(r != want))
+            else:
+                check_p2p(r[0], r[1], want, want_d, prec, f"{prec} cs={cs}")
+    tx, ty = dev_arrays(px, py)
+    best, rows = gp.gp_sweep_cell_size(kind, g, base, sizes, tx, ty, "mixed")
+    say("  sweep", best, rows)
+    assert best in sizes
+    assert all(r["ms"] > 0 and r["pairs"] > 0 and r["grid_bytes"] > 0 for r in rows)
+    tests = [r["tests"] for r in rows]
+    order = np.argsort(sizes)
+    assert all(tests[order[i]] <= tests[order[i + 1]] for i in range(len(sizes) - 1)), rows
+
+
 def test_near_edge_sweep_mixed(gp):
     """Points at distances 1e-15 .. 1e-3 (relative to the unit square) from polygon
     edges, on both sides: the guard band must send every doubtful one to FP64."""
