@@ -123,6 +123,9 @@ typedef struct gp_tuning {
     int32_t persistent;      /* 1: persistent work queue; 0: one workgroup per item */
     int32_t waves_per_item;  /* P2P: 1, 2 or 4 wavefronts share one LDS staging and a work
                                 item holds up to 64*ppl*waves points; PIP: always 1 */
+    int32_t vp_points;       /* PIP: items with at most this many points (1..64) use the
+                                vertex-parallel mapping (lanes over edges, FP64, Sec.
+                                III.B's alternative); -1 never; 0 = library default */
 } gp_tuning;
 
 /* Per-call counters.  Filling them synchronises the stream at the end of the call. */

@@ -68,6 +68,7 @@ static gp_tuning default_tuning(gp_kind kind, gp_precision prec) {
   t.wg_per_cu = (prec == GP_MIXED && kind == GP_P2P) ? 32 : 16;
   t.persistent = (prec == GP_MIXED && kind == GP_PIP) ? 0 : 1;
   t.waves_per_item = 1;
+  t.vp_points = kind == GP_PIP ? 16 : -1;
   return t;
 }
 
@@ -76,7 +77,8 @@ static bool tuning_valid(const gp_tuning &t, gp_kind kind) {
   return (t.points_per_lane == 1 || t.points_per_lane == 2 || t.points_per_lane == 4) &&
          t.edge_chunk >= 64 && t.edge_chunk <= 512 && t.edge_chunk % 64 == 0 &&
          t.wg_per_cu >= 1 && t.wg_per_cu <= 32 && (t.persistent == 0 || t.persistent == 1) &&
-         (w == 1 || (kind == GP_P2P && (w == 2 || w == 4)));
+         (w == 1 || (kind == GP_P2P && (w == 2 || w == 4))) &&
+         (t.vp_points == -1 || (kind == GP_PIP && t.vp_points >= 1 && t.vp_points <= 64));
 }
 
 // ------------------------------------------------------------------------- geometry checks
@@ -542,6 +544,7 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   a.rq = w.rq;
   a.rq_count = w.counters + C_RQ;
   a.edge_chunk = t.edge_chunk;
+  a.vp_points = t.vp_points;
 
   GP_TRY_HIP(launch_unpaired(a, n, w.counters + C_NPAIRED, s));
   GP_TRY_HIP(launch_items(w.pt_off, g->d_cand_off, g->d_cell_edges, g->d_cell_edges_all,
@@ -638,6 +641,7 @@ extern "C" gp_status gp_set_tuning(gp_grid *g, gp_precision prec, const gp_tunin
   if (v.edge_chunk == 0) v.edge_chunk = d.edge_chunk;
   if (v.wg_per_cu == 0) v.wg_per_cu = d.wg_per_cu;
   if (v.waves_per_item == 0) v.waves_per_item = d.waves_per_item;
+  if (v.vp_points == 0) v.vp_points = d.vp_points;
   if (!tuning_valid(v, g->kind)) return set_error(GP_E_INVALID_ARG, "invalid tuning");
   g->tune[prec] = v;
   return GP_OK;
@@ -666,14 +670,16 @@ extern "C" gp_status gp_autotune(gp_grid *g, gp_precision prec, int64_t n, const
   const int ppls[3] = {1, 2, 4}, ecs[3] = {128, 256, 512}, wgs[4] = {8, 12, 16, 32};
   for (int p : ppls)
     for (int e : ecs)
-      for (int wgc : wgs) space.push_back(gp_tuning{p, e, wgc, 1, 1});
+      for (int wgc : wgs) space.push_back(gp_tuning{p, e, wgc, 1, 1, 0});
   for (int p : ppls)
-    for (int e : ecs) space.push_back(gp_tuning{p, e, 16, 0, 1});
+    for (int e : ecs) space.push_back(gp_tuning{p, e, 16, 0, 1, 0});
   if (g->kind == GP_P2P)
     for (int wv : {2, 4})
       for (int p : ppls)
         for (int e : ecs)
-          for (int wgc : {4, 8, 16}) space.push_back(gp_tuning{p, e, wgc, 1, wv});
+          for (int wgc : {4, 8, 16}) space.push_back(gp_tuning{p, e, wgc, 1, wv, 0});
+  const int vp_default = default_tuning(g->kind, prec).vp_points;
+  for (gp_tuning &t : space) t.vp_points = vp_default;
   float best_t = INFINITY;
   gp_tuning best_cfg = g->tune[prec];
   for (const gp_tuning &t : space) {
@@ -689,6 +695,26 @@ extern "C" gp_status gp_autotune(gp_grid *g, gp_precision prec, int64_t n, const
     if (times[1] < best_t) {
       best_t = times[1];
       best_cfg = t;
+    }
+  }
+  if (g->kind == GP_PIP) {
+    // then the vertex-parallel threshold, on the best configuration
+    for (int vp : {-1, 4, 8, 32, 64}) {
+      gp_tuning t = best_cfg;
+      t.vp_points = vp;
+      float times[3];
+      for (int r = 0; r < 4; ++r) {
+        gp_stats st;
+        gp_status rc = run_query(g, g->kind, n, px, py, d_id.as<int32_t>(), d_dist.as<double>(),
+                                 prec, ws, ws_bytes, s, &st, &t);
+        if (rc) return rc;
+        if (r > 0) times[r - 1] = st.ms_total;
+      }
+      std::sort(times, times + 3);
+      if (times[1] < best_t) {
+        best_t = times[1];
+        best_cfg = t;
+      }
     }
   }
   g->tune[prec] = best_cfg;

@@ -56,6 +56,7 @@ struct RefineArgs {
   uint32_t *rq;
   uint32_t *rq_count;
   int32_t edge_chunk;
+  int32_t vp_points;         // PIP: items with at most this many points go vertex-parallel
 };
 
 // Device-resident grid.

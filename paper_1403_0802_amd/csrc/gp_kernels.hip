@@ -866,8 +866,65 @@ struct alignas(16) PipRec64 {
   double lox, loy, hiy, w, h, pad;
 };
 
+// Vertex-parallel refinement of an item with few points (the alternative mapping of
+// Sec. III.B): lanes take the edges of a candidate polygon, the wave loops over the
+// item's points (lane p holds point p and its parity), and a point's crossing parity
+// over a chunk of 64 edges is the popcount of one ballot.  FP64 in the definition's
+// operation order, so its results are final in both precision forms.
+__device__ void pip_vp_item(const RefineArgs &a, const Item it) {
+  const uint32_t lane = lane_id();
+  const int np = it.npts;  // <= a.vp_points <= 64
+  double qx = 0.0, qy = 0.0;
+  if ((int)lane < np) {
+    const double2 p = a.xy[it.pt_lo + (int)lane];
+    qx = p.x;
+    qy = p.y;
+  }
+  int32_t best = -1;
+  const int32_t k0 = a.cand_off[it.cell], k1 = a.cand_off[it.cell + 1];
+  for (int32_t k = k0; k < k1; ++k) {
+    const int32_t f = a.cand_id[k];
+    const int cls = a.cand_class ? a.cand_class[k] : 2;
+    if (cls == 0) continue;  // the cell lies outside polygon f
+    if (cls == 1) {          // inside: every undecided point takes f
+      if (best < 0) best = f;
+      break;
+    }
+    uint32_t par = 0;
+    const int32_t e1 = a.eoff[f + 1];
+    for (int32_t e0 = a.eoff[f]; e0 < e1; e0 += GP_WAVE) {
+      const int32_t e = e0 + (int32_t)lane;
+      const bool act = e < e1;
+      double lox = 0.0, loy = 0.0, w = 0.0, hiy = 0.0, h = 0.0;
+      if (act) {
+        const double4 r = a.edge64[e];
+        lox = r.x;
+        loy = r.y;
+        w = r.z - r.x;
+        hiy = r.w;
+        h = r.w - r.y;
+      }
+      for (int p = 0; p < np; ++p) {
+        const double px = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(qx), p),
+                                           __builtin_amdgcn_readlane(__double2loint(qx), p));
+        const double py = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(qy), p),
+                                           __builtin_amdgcn_readlane(__double2loint(qy), p));
+        const bool c = act && cross64(px, py, lox, loy, w, hiy, h);
+        const uint32_t odd = (uint32_t)__popcll(ballot(c)) & 1u;
+        if ((int)lane == p) par ^= odd;
+      }
+    }
+    if ((int)lane < np && best < 0 && par) best = f;
+  }
+  if ((int)lane < np) a.out_id[a.perm[it.pt_lo + (int)lane]] = best;
+}
+
 template <int PPL>
 __device__ void pip64_item(const RefineArgs &a, const Item it, PipRec64 *lds) {
+  if (it.npts <= a.vp_points) {
+    pip_vp_item(a, it);
+    return;
+  }
   const uint32_t lane = lane_id();
   const int EC = a.edge_chunk;
   double px[PPL], py[PPL];
@@ -949,6 +1006,10 @@ __device__ __forceinline__ uint64_t plain_cross(float px, float py, const float4
 template <int PPL>
 __device__ void pipmix_item(const RefineArgs &a, const Item it, float4 *ldsA, float4 *ldsB,
                             float *ldsG) {
+  if (it.npts <= a.vp_points) {
+    pip_vp_item(a, it);
+    return;
+  }
   const uint32_t lane = lane_id();
   const int EC = a.edge_chunk;
   const double cx = cell_cx(a, (uint32_t)it.cell), cy = cell_cy(a, (uint32_t)it.cell);

@@ -128,6 +128,12 @@ static gp_status enqueue_chunk(gp_server *srv, Slot &sl, Request *r, int64_t lo,
   const gp_precision prec = (gp_precision)o.precision;
   Workspace w;
   workspace_layout(*(const Grid *)g, b, prec, sl.ws, &w);
+  // A request's points spread over the grid's cells, so a small bucket has few points
+  // per cell: keep work items to one wavefront and fewer points per lane there.
+  gp_tuning tn = ((const Grid *)g)->tune[prec];
+  tn.waves_per_item = 1;
+  const int ppl_cap = b >= (1 << 20) ? 4 : b >= (1 << 17) ? 2 : 1;
+  if (tn.points_per_lane > ppl_cap) tn.points_per_lane = ppl_cap;
   if (o.use_graphs) {
     auto key = std::make_pair((int)r->kind, b);
     auto it = sl.graphs.find(key);
@@ -135,7 +141,7 @@ static gp_status enqueue_chunk(gp_server *srv, Slot &sl, Request *r, int64_t lo,
       hipGraph_t graph;
       SV_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       gp_status rc = run_query_tuned(g, r->kind, b, sl.px, sl.py, sl.id, sl.dist, prec, sl.ws,
-                                     sl.ws_bytes, s, nullptr, nullptr);
+                                     sl.ws_bytes, s, nullptr, &tn);
       hipError_t ec = hipStreamEndCapture(s, &graph);
       if (rc) return rc;
       SV_TRY(ec);
@@ -148,7 +154,7 @@ static gp_status enqueue_chunk(gp_server *srv, Slot &sl, Request *r, int64_t lo,
     srv->replays++;
   } else {
     gp_status rc = run_query_tuned(g, r->kind, b, sl.px, sl.py, sl.id, sl.dist, prec, sl.ws,
-                                   sl.ws_bytes, s, nullptr, nullptr);
+                                   sl.ws_bytes, s, nullptr, &tn);
     if (rc) return rc;
   }
   SV_TRY(hipMemcpyAsync(r->out_id + lo, sl.id, (size_t)m * 4, out_kind, s));

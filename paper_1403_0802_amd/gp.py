@@ -51,7 +51,7 @@ class gp_grid_params(Structure):
 
 class gp_tuning(Structure):
     _fields_ = [("points_per_lane", c_int32), ("edge_chunk", c_int32), ("wg_per_cu", c_int32),
-                ("persistent", c_int32), ("waves_per_item", c_int32)]
+                ("persistent", c_int32), ("waves_per_item", c_int32), ("vp_points", c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -246,8 +246,8 @@ def gp_p2p(grid, px, py, out_id, out_dist, prec, ws, stream=None, stats: bool = 
 
 
 def gp_set_tuning(grid, prec, points_per_lane=0, edge_chunk=0, wg_per_cu=0, persistent=1,
-                  waves_per_item=0):
-    t = gp_tuning(points_per_lane, edge_chunk, wg_per_cu, persistent, waves_per_item)
+                  waves_per_item=0, vp_points=0):
+    t = gp_tuning(points_per_lane, edge_chunk, wg_per_cu, persistent, waves_per_item, vp_points)
     check(lib.gp_set_tuning(grid.handle, PRECISIONS.get(prec, prec), ctypes.byref(t)))
 
 

@@ -154,6 +154,11 @@ TUNINGS_P2P = TUNINGS + [dict(points_per_lane=p, edge_chunk=e, wg_per_cu=wg, per
                               waves_per_item=wv)
                          for wv in (2, 4) for p in (1, 4) for e in (64, 512)
                          for wg, pe in ((4, 1), (8, 0))]
+# PIP items with few points may go vertex-parallel (lanes over edges): never, always
+# (64), and thresholds in between, with both point-parallel shapes around them
+TUNINGS_PIP = TUNINGS + [dict(points_per_lane=p, edge_chunk=128, wg_per_cu=8, persistent=pe,
+                              vp_points=vp)
+                         for vp in (-1, 1, 5, 16, 64) for p in (1, 4) for pe in (0, 1)]
 
 
 @pytest.mark.parametrize("kind", ["pip", "p2p"])
@@ -169,7 +174,7 @@ def test_results_invariant_under_tuning(gp, kind):
     grid = gp.gp_build_grid(kind, w.geom, w.params)
     for prec in ("fp64", "mixed"):
         ref = None
-        for t in (TUNINGS if kind == "pip" else TUNINGS_P2P):
+        for t in (TUNINGS_PIP if kind == "pip" else TUNINGS_P2P):
             r = run_gpu(gp, grid, w.px, w.py, prec, tuning=t)
             if kind == "pip":
                 assert np.array_equal(r, want), (prec, t)
