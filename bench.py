@@ -165,6 +165,31 @@ def cpu_baseline(c3, c4, budget_s: float):
     }
 
 
+def cpu_simd_run(c3, c4, budget_s: float):
+    """The host implementation in the paper's four CPU modes (single core / all cores,
+    scalar / AVX-512), on prefixes of the same point sets sized for about budget_s/8 of
+    refinement each; rates are tests per second of refinement."""
+    from paper_1403_0802_amd import cpu
+    threads = len(os.sched_getaffinity(0))
+    out = {"simd_available": cpu.gp_cpu_has_simd(), "threads": threads, "modes": {}}
+    per = budget_s / 8
+    for mode in ("sc", "mc", "sc_simd", "mc_simd"):
+        row = {}
+        for name, (geom, p, px, py), m0 in (("pip", c3, 20_000), ("p2p", c4, 20_000)):
+            _, _, st = cpu.gp_cpu_join(name, geom, p, px[:m0], py[:m0], mode, threads)
+            rate = st["tests"] / max(st["ms_refine"] / 1e3, 1e-6)
+            per_pt = max(st["tests"] / m0, 1.0)
+            m = int(min(len(px), max(m0, per * rate / per_pt)))
+            _, _, st = cpu.gp_cpu_join(name, geom, p, px[:m], py[:m], mode, threads)
+            row[name] = {"points": m, "tests": st["tests"], "ms_refine": st["ms_refine"],
+                         "tests_per_s": st["tests"] / max(st["ms_refine"] / 1e3, 1e-9),
+                         "simd": st["simd"], "threads": st["threads"]}
+        out["modes"][mode] = row
+        log(f"[bench] cpu {mode}: pip {row['pip']['tests_per_s']:.3g} tests/s, "
+            f"p2p {row['p2p']['tests_per_s']:.3g} tests/s")
+    return out
+
+
 def serving_run(gp, torch, grid3, grid4, n_requests: int, precision: str):
     """Configuration 5: a Poisson stream of mixed PIP/P2P batches (log-uniform 1K-4M
     points) against the resident grids, offered at ~70% of the rate sustained during
@@ -239,6 +264,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-cpu-simd", action="store_true",
+                    help="skip the host SIMD/multi-core implementation's four modes")
     ap.add_argument("--no-classes", action="store_true",
                     help="skip the PIP cell-classification measurement")
     ap.add_argument("--copy-probe", action="store_true",
@@ -447,6 +474,9 @@ def main():
     if not args.no_cpu:
         log("[bench] cpu baseline")
         out["cpu_baseline"] = cpu_baseline(c3, c4, args.cpu_budget)
+        if not args.no_cpu_simd:
+            log("[bench] cpu simd modes")
+            detail["cpu_simd"] = cpu_simd_run(c3, c4, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

@@ -39,6 +39,27 @@ def _compile(src: str) -> str:
     return obj
 
 
+CPU_SRC = os.path.join(HERE, "cpu", "gp_cpu.cpp")
+CPU_LIB = os.path.join(HERE, "libgp_cpu.so")
+CPU_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+             "-Wall", "-Wextra"]
+
+
+def build_cpu(verbose: bool = False) -> str:
+    """The host SIMD/multi-core implementation (libgp_cpu.so).  Its AVX-512 functions
+    carry their own target attribute, so the library runs, scalar, on any x86-64."""
+    tmp = CPU_LIB + ".tmp"
+    r = subprocess.run(["g++", *CPU_FLAGS, CPU_SRC, "-o", tmp], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("build of libgp_cpu.so failed:\n" + r.stdout + r.stderr)
+    if (r.stdout + r.stderr).strip():
+        print(r.stdout + r.stderr, file=sys.stderr)
+    os.replace(tmp, CPU_LIB)
+    if verbose:
+        print("built", CPU_LIB)
+    return CPU_LIB
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(len(SOURCES)) as ex:
@@ -56,3 +77,4 @@ def build(verbose: bool = False) -> str:
 
 if __name__ == "__main__":
     build(verbose=True)
+    build_cpu(verbose=True)

@@ -10,8 +10,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "gp.h")
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(gp_\w+)\s*\(", text, flags=re.M)
     return sorted(set(names))
@@ -30,6 +30,15 @@ def test_library_exports_every_declared_symbol():
     for n in declared_functions():
         assert hasattr(lib, n), n
     assert sorted(declared_functions()) == gp.EXPORTED
+
+
+def test_cpu_library_exports_its_header():
+    from paper_1403_0802_amd import cpu
+    names = declared_functions(os.path.join(ROOT, "include", "gp_cpu.h"))
+    lib = ctypes.CDLL(cpu.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(names) == sorted(cpu.EXPORTED)
 
 
 def test_argument_errors_are_synchronous():
@@ -65,12 +74,13 @@ def test_argument_errors_are_synchronous():
 def test_oracle_and_gpu_path_share_no_code():
     """The HIP sources never include or name the oracle, and the oracle never loads the
     HIP library."""
-    csrc = os.path.join(ROOT, "paper_1403_0802_amd", "csrc")
-    for f in os.listdir(csrc):
-        text = open(os.path.join(csrc, f)).read()
-        assert "oracle" not in text.lower(), f
+    for sub in ("csrc", "cpu"):
+        src = os.path.join(ROOT, "paper_1403_0802_amd", sub)
+        for f in os.listdir(src):
+            text = open(os.path.join(src, f)).read()
+            assert "oracle" not in text.lower(), f
     pkg = os.path.join(ROOT, "paper_1403_0802_amd")
-    for f in ("gp.py", "build.py", "synth.py", "__init__.py"):
+    for f in ("gp.py", "cpu.py", "build.py", "synth.py", "__init__.py"):
         assert "import oracle" not in open(os.path.join(pkg, f)).read()
     for f in os.listdir(os.path.join(ROOT, "oracle")):
         if f.endswith((".py", ".c")):
