@@ -104,13 +104,20 @@ typedef struct gp_geometry {
  * centre; every other pair is a boundary pair.  Queries then skip outside pairs, give
  * every still undecided point of the cell an inside pair's id without testing, and test
  * only boundary pairs.  Results are identical to the unclassified grid; gp_stats.tests
- * counts the tests performed and tests_avoided the candidate tests skipped. */
+ * counts the tests performed and tests_avoided the candidate tests skipped.
+ * p2p_segment_filter = 1 (P2P only; 0 otherwise) also rasterises every segment's
+ * bounding box, expanded by D and padded like the MBBs, and keeps per cell the list of
+ * segments it reaches; the GP_MIXED form then tests only those (a segment farther than
+ * D from the whole cell can neither be a point's nearest segment within range nor bring
+ * a polyline into range), with the same results; tests and tests_avoided as above.  The
+ * GP_FP64 form keeps testing every candidate segment. */
 typedef struct gp_grid_params {
     double cell_size;
     double radius_D;
     double x0, y0;
     int64_t nx, ny;
     int32_t pip_cell_classes;
+    int32_t p2p_segment_filter;
 } gp_grid_params;
 
 typedef struct gp_grid gp_grid;
@@ -161,6 +168,7 @@ typedef struct gp_grid_info {
     int64_t nx, ny, n_features, n_edges, n_pairs;
     int64_t n_pairs_inside, n_pairs_outside, n_pairs_boundary; /* cell classes, else 0 */
     int64_t device_bytes;  /* device memory the grid holds */
+    int64_t n_segment_pairs; /* (cell, segment) pairs of p2p_segment_filter, else 0 */
 } gp_grid_info;
 gp_status gp_grid_get_info(const gp_grid *grid, gp_grid_info *info);
 

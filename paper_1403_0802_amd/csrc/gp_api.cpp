@@ -128,6 +128,8 @@ extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
   if (params->nx < 0 || params->ny < 0) return set_error(GP_E_INVALID_ARG, "negative nx/ny");
   if (params->pip_cell_classes != 0 && params->pip_cell_classes != 1)
     return set_error(GP_E_INVALID_ARG, "pip_cell_classes must be 0 or 1");
+  if (params->p2p_segment_filter != 0 && params->p2p_segment_filter != 1)
+    return set_error(GP_E_INVALID_ARG, "p2p_segment_filter must be 0 or 1");
   const bool derive = params->nx == 0 || params->ny == 0;
   if (!derive && (!std::isfinite(params->x0) || !std::isfinite(params->y0)))
     return set_error(GP_E_INVALID_ARG, "non-finite grid origin");
@@ -345,6 +347,53 @@ extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
                                    ncells, g->d_cell_edges, s));
     GP_TRY_HIP_G(hipStreamSynchronize(s));
   }
+  if (kind == GP_P2P && params->p2p_segment_filter && nedges > 0) {
+    // (cell, segment) pairs: every segment's box, expanded by D and padded like the MBBs,
+    // rasterised and stably sorted by cell, so each cell lists its segments ascending
+    const int32_t ns = (int32_t)nedges;
+    DevBuf box, cnt, tmp;
+    GP_TRY_HIP_G(box.alloc((size_t)ns * 32));
+    GP_TRY_HIP_G(cnt.alloc(((size_t)ns + 1) * 4));
+    GP_TRY_HIP_G(tmp.alloc(scan_tmp_elems(std::max((size_t)ns + 1, (size_t)ncells + 1)) * 4));
+    GP_TRY_HIP_G(launch_seg_boxes(g->d_edge64, ns, D, cs * 0x1p-20, box.as<double>(), s));
+    GP_TRY_HIP_G(launch_raster_count(box.as<double>(), ns, x0, y0, cs, g->nx, g->ny,
+                                     cnt.as<uint32_t>(), s));
+    GP_TRY_HIP_G(launch_exclusive_scan_u32(cnt.as<uint32_t>(), cnt.as<uint32_t>(),
+                                           (size_t)ns + 1, tmp.as<uint32_t>(), s));
+    uint32_t np2 = 0;
+    GP_TRY_HIP_G(hipMemcpyAsync(&np2, cnt.as<uint32_t>() + ns, 4, hipMemcpyDeviceToHost, s));
+    GP_TRY_HIP_G(hipStreamSynchronize(s));
+    if (np2 >= (uint32_t)kMaxCount)
+      return fail(set_error(GP_E_CAPACITY, "too many (cell, segment) pairs"));
+    g->ncseg = np2;
+    const size_t n2 = std::max<size_t>(np2, 1);
+    DevBuf kA, kB, vA, vB, hist, stmp;
+    GP_TRY_HIP_G(kA.alloc(n2 * 4));
+    GP_TRY_HIP_G(kB.alloc(n2 * 4));
+    GP_TRY_HIP_G(vA.alloc(n2 * 4));
+    GP_TRY_HIP_G(vB.alloc(n2 * 4));
+    GP_TRY_HIP_G(hist.alloc(radix_hist_elems(n2) * 4));
+    GP_TRY_HIP_G(stmp.alloc(scan_tmp_elems(std::max(radix_hist_elems(n2), (size_t)ncells + 1)) * 4));
+    GP_TRY_HIP_G(launch_raster_emit(box.as<double>(), ns, x0, y0, cs, g->nx, g->ny,
+                                    cnt.as<uint32_t>(), kA.as<uint32_t>(), vA.as<uint32_t>(), s));
+    uint32_t *skeys = nullptr, *svals = nullptr;
+    GP_TRY_HIP_G(launch_radix_sort(kA.as<uint32_t>(), kB.as<uint32_t>(), vA.as<uint32_t>(),
+                                   vB.as<uint32_t>(), np2, bits_for((uint64_t)ncells - 1), false,
+                                   hist.as<uint32_t>(), stmp.as<uint32_t>(), s, &skeys, &svals));
+    GP_TRY_HIP_G(hipMalloc(&g->d_cseg_off, ((size_t)ncells + 1) * 4));
+    GP_TRY_HIP_G(hipMalloc(&g->d_cseg, n2 * 4));
+    GP_TRY_HIP_G(hipMalloc(&g->d_seg2f, (size_t)ns * 4));
+    GP_TRY_HIP_G(hipMalloc(&g->d_cell_segs, std::max<size_t>(ncells, 1) * 8));
+    GP_TRY_HIP_G(launch_fill_u32((uint32_t *)g->d_cseg_off, 0u, (size_t)ncells + 1, s));
+    GP_TRY_HIP_G(launch_histogram(skeys, np2, (uint32_t *)g->d_cseg_off, s));
+    GP_TRY_HIP_G(launch_exclusive_scan_u32((uint32_t *)g->d_cseg_off, (uint32_t *)g->d_cseg_off,
+                                           (size_t)ncells + 1, stmp.as<uint32_t>(), s));
+    if (np2)
+      GP_TRY_HIP_G(hipMemcpyAsync(g->d_cseg, svals, (size_t)np2 * 4, hipMemcpyDeviceToDevice, s));
+    GP_TRY_HIP_G(launch_seg2f(g->d_eoff, (int32_t)nf, g->d_seg2f, s));
+    GP_TRY_HIP_G(launch_cell_counts(g->d_cseg_off, ncells, g->d_cell_segs, s));
+    GP_TRY_HIP_G(hipStreamSynchronize(s));
+  }
 #undef GP_TRY_HIP_G
   *out = g;
   return GP_OK;
@@ -363,6 +412,10 @@ extern "C" void gp_grid_free(gp_grid *g) {
   (void)hipFree(g->d_cell_edges);
   (void)hipFree(g->d_cell_edges_all);
   (void)hipFree(g->d_cand_class);
+  (void)hipFree(g->d_cseg_off);
+  (void)hipFree(g->d_cseg);
+  (void)hipFree(g->d_seg2f);
+  (void)hipFree(g->d_cell_segs);
   delete g;
 }
 
@@ -373,6 +426,7 @@ static int64_t grid_device_bytes(const Grid &g) {
   int64_t b = ((int64_t)g.nf + 1) * 4 + ne * (32 + 4) + (nc + 1) * 4 + np * 4 + nc * 8;
   if (g.kind == GP_P2P) b += ne * (32 + 16) + (ne + P2P_BLOCK - 1) / P2P_BLOCK * 32;
   if (g.d_cand_class) b += np + nc * 8;
+  if (g.d_cseg_off) b += (nc + 1) * 4 + std::max<int64_t>(g.ncseg, 1) * 4 + ne * 4 + nc * 8;
   return b;
 }
 
@@ -392,6 +446,7 @@ extern "C" gp_status gp_grid_get_info(const gp_grid *g, gp_grid_info *info) {
   info->n_pairs_inside = g->npairs_class[1];
   info->n_pairs_boundary = g->d_cand_class ? g->npairs_class[2] : 0;
   info->device_bytes = grid_device_bytes(*g);
+  info->n_segment_pairs = g->ncseg;
   return GP_OK;
 }
 
@@ -525,6 +580,10 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   a.frame32 = g->d_frame32;
   a.circ = g->d_circ;
   a.cand_class = g->d_cand_class;
+  const bool segf = prec == GP_MIXED && g->d_cseg_off != nullptr;
+  a.cseg_off = segf ? g->d_cseg_off : nullptr;
+  a.cseg = segf ? g->d_cseg : nullptr;
+  a.seg2f = segf ? g->d_seg2f : nullptr;
   a.x0 = g->x0;
   a.y0 = g->y0;
   a.cs = g->cs;
@@ -547,8 +606,8 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   a.vp_points = t.vp_points;
 
   GP_TRY_HIP(launch_unpaired(a, n, w.counters + C_NPAIRED, s));
-  GP_TRY_HIP(launch_items(w.pt_off, g->d_cand_off, g->d_cell_edges, g->d_cell_edges_all,
-                          g->ncells,
+  GP_TRY_HIP(launch_items(w.pt_off, g->d_cand_off, segf ? g->d_cell_segs : g->d_cell_edges,
+                          segf ? g->d_cell_edges : g->d_cell_edges_all, g->ncells,
                           64 * t.points_per_lane * t.waves_per_item, w.item_cnt, w.scan_tmp,
                           w.items, w.counters, w.tests, s));
   if (stats) GP_TRY_HIP(hipEventRecord(ev[1], s));
@@ -575,7 +634,7 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
     stats->n_paired = cnt[C_NPAIRED];
     stats->n_items = nitems;
     stats->tests = tests[0];
-    stats->tests_avoided = g->d_cell_edges_all ? tests[1] - tests[0] : 0;
+    stats->tests_avoided = (g->d_cell_edges_all || segf) ? tests[1] - tests[0] : 0;
     stats->n_rechecked = prec == GP_MIXED ? cnt[C_RQ] : 0;
     stats->ms_pairing = m01;
     stats->ms_refine = m12;

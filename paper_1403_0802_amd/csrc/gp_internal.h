@@ -39,6 +39,9 @@ struct RefineArgs {
   const float4 *frame32;     // P2P: (u.x*scale, u.y*scale, |d|/2*scale, |d|)
   const double4 *circ;       // P2P: per block of P2P_BLOCK segments (centre x, y, radius, 0)
   const uint8_t *cand_class; // PIP, optional: per candidate pair 0 outside, 1 inside, 2 boundary
+  const int32_t *cseg_off;   // P2P mixed, optional: [ncells+1] into cseg
+  const int32_t *cseg;       // the segments that reach each cell, ascending
+  const int32_t *seg2f;      // [nseg] polyline of each segment
   double x0, y0, cs;
   int32_t nx, ncells;
   double D, D2, D2_next;     // P2P: D, fl(D*D), the smallest double above fl(D*D)
@@ -78,6 +81,11 @@ struct Grid {
   int64_t *d_cell_edges_all;  // [ncells] over all candidates (only with cell classes)
   uint8_t *d_cand_class;  // [npairs] PIP cell classes, or null
   int64_t npairs_class[3];  // outside, inside, boundary
+  int32_t *d_cseg_off;    // P2P segment filter: [ncells+1]
+  int32_t *d_cseg;        // [ncseg]
+  int32_t *d_seg2f;       // [nedges]
+  int64_t *d_cell_segs;   // [ncells] segments per cell
+  int64_t ncseg;
   float p2p_scale;        // see RefineArgs
   gp_tuning tune[2];
   int num_cu;
@@ -139,6 +147,10 @@ hipError_t launch_histogram(const uint32_t *keys, size_t n, uint32_t *cnt, hipSt
 hipError_t launch_cell_edges(const int32_t *cand_off, const int32_t *cand_id,
                              const int32_t *eoff, const uint8_t *cand_class, int32_t ncells,
                              int64_t *cell_edges, hipStream_t s);
+hipError_t launch_seg_boxes(const double4 *seg64, int32_t nseg, double D, double pad,
+                            double *box, hipStream_t s);
+hipError_t launch_seg2f(const int32_t *eoff, int32_t nf, int32_t *seg2f, hipStream_t s);
+hipError_t launch_cell_counts(const int32_t *off, int32_t ncells, int64_t *cnt, hipStream_t s);
 hipError_t launch_classify_pairs(const uint32_t *pair_cell, const int32_t *cand_id,
                                  int32_t npairs, const int32_t *eoff, const double4 *edge64,
                                  double x0, double y0, double cs, int32_t nx, double margin,

@@ -409,6 +409,49 @@ hipError_t launch_build_circles(const double4 *seg64, int32_t nseg, double4 *cir
   return hipGetLastError();
 }
 
+// Bounding box of each segment, expanded by D and padded like the feature MBBs, in the
+// MBB layout the rasteriser takes.
+__global__ void k_seg_boxes(const double4 *seg, int32_t nseg, double D, double pad, double *box) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += gridDim.x * blockDim.x) {
+    const double4 r = seg[i];
+    box[4 * (size_t)i + 0] = (fmin(r.x, r.z) - D) - pad;
+    box[4 * (size_t)i + 1] = (fmin(r.y, r.w) - D) - pad;
+    box[4 * (size_t)i + 2] = (fmax(r.x, r.z) + D) + pad;
+    box[4 * (size_t)i + 3] = (fmax(r.y, r.w) + D) + pad;
+  }
+}
+
+hipError_t launch_seg_boxes(const double4 *seg64, int32_t nseg, double D, double pad,
+                            double *box, hipStream_t s) {
+  if (nseg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seg_boxes, dim3(grid_for(nseg, 256, 8192)), dim3(256), 0, s, seg64, nseg,
+                     D, pad, box);
+  return hipGetLastError();
+}
+
+// Polyline of each segment (segments are stored polyline by polyline).
+__global__ void k_seg2f(const int32_t *eoff, int32_t nf, int32_t *seg2f) {
+  for (int32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += gridDim.x * blockDim.x)
+    for (int32_t e = eoff[f]; e < eoff[f + 1]; ++e) seg2f[e] = f;
+}
+
+hipError_t launch_seg2f(const int32_t *eoff, int32_t nf, int32_t *seg2f, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seg2f, dim3(grid_for(nf, 256, 8192)), dim3(256), 0, s, eoff, nf, seg2f);
+  return hipGetLastError();
+}
+
+__global__ void k_cell_counts(const int32_t *off, int32_t ncells, int64_t *cnt) {
+  for (int32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncells; c += gridDim.x * blockDim.x)
+    cnt[c] = (int64_t)(off[c + 1] - off[c]);
+}
+
+hipError_t launch_cell_counts(const int32_t *off, int32_t ncells, int64_t *cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_counts, dim3(grid_for(ncells, 256, 8192)), dim3(256), 0, s, off,
+                     ncells, cnt);
+  return hipGetLastError();
+}
+
 // Feature MBB over all of its vertices; P2P expands by D; both pad by cs*2^-20.
 __global__ void k_mbb(const int32_t *rvo, const int32_t *fro, const double *x, const double *y,
                       int32_t nf, int kind, double D, double cs, double *mbb) {
@@ -1279,7 +1322,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 template <int PPL, int W>
 __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, float *ldsV,
-                            int2 *tab, int *slotseg, float *red, unsigned char *epi) {
+                            int2 *tab, int *slotseg, int *slotf, float *red, unsigned char *epi) {
   const int tid = (int)threadIdx.x;
   const uint32_t lane = lane_id();
   const int wave = (int)(threadIdx.x / GP_WAVE);
@@ -1331,8 +1374,11 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
     const bool nearc = !(ex * ex + fr * fr > near_lim2) || !(es <= 0.5f * T);
     if (nearc) emax = fmaxf(emax, es);
   };
-  int32_t k = a.cand_off[it.cell];
-  const int32_t k1 = a.cand_off[it.cell + 1];
+  // With a segment filter the cell's chunks are slices of its list of reaching segments;
+  // otherwise they are cut from its candidate polylines' whole segment ranges.
+  const bool seglist = a.cseg_off != nullptr;
+  int32_t k = seglist ? a.cseg_off[it.cell] : a.cand_off[it.cell];
+  const int32_t k1 = seglist ? a.cseg_off[it.cell + 1] : a.cand_off[it.cell + 1];
   int32_t soff = 0;
   // Candidate window: lane i of each wave holds candidate kw + i (id, first and end
   // segment), fetched in one round trip, so planning a chunk issues no dependent loads.
@@ -1340,7 +1386,37 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
   while (k < k1) {
     __syncthreads();
     int filled = 0, ntab = 0;
-    while (k < k1 && filled < EC) {
+    if (seglist) {
+      // the slot map is the list slice; a polyline's entries are consecutive (segments
+      // are stored polyline by polyline), so it ends where the next entry's polyline
+      // differs, or continues into the next chunk
+      filled = (k1 - k) < EC ? (k1 - k) : EC;
+      for (int t = tid; t < filled; t += GP_WAVE * W) {
+        const int32_t sg = a.cseg[k + t];
+        slotseg[t] = sg;
+        slotf[t] = a.seg2f[sg];
+      }
+      const int32_t fnext = k + filled < k1 ? a.seg2f[a.cseg[k + filled]] : -1;
+      __syncthreads();
+      for (int base = 0; base < filled; base += GP_WAVE) {
+        const int t = base + (int)lane;
+        int32_t ft = -1;
+        bool mark = false, cont = false;
+        if (t < filled) {
+          ft = slotf[t];
+          const int32_t fn = t + 1 < filled ? slotf[t + 1] : fnext;
+          mark = fn != ft || t == filled - 1;
+          cont = t == filled - 1 && fn == ft;
+        }
+        const uint64_t m = ballot(mark);
+        if (mark && wave == 0)
+          tab[ntab + (int)__popcll(m & lanemask_lt())] =
+              make_int2(ft, (t + 1) | (cont ? (int)0x80000000 : 0));
+        ntab += (int)__popcll(m);
+      }
+      k += filled;
+    }
+    while (!seglist && k < k1 && filled < EC) {
       if (k >= kw + GP_WAVE || kw == k1) {
         kw = k;
         const int32_t kk = kw + (int)lane;
@@ -1620,10 +1696,11 @@ __global__ __launch_bounds__(64 * W) void k_p2pmix(RefineArgs a, int persistent)
   float *V = (float *)(U + a.edge_chunk);
   int2 *tab = (int2 *)(V + a.edge_chunk);
   int *slotseg = (int *)(tab + a.edge_chunk);
+  int *slotf = slotseg + a.edge_chunk;
   const uint32_t n_items = *a.n_items;
   uint32_t it = persistent ? (W == 1 ? next_item(a) : next_item_wg(a, &s_item)) : blockIdx.x;
   while (it < n_items) {
-    p2pmix_item<PPL, W>(a, a.items[it], U, V, tab, slotseg, red, smem);
+    p2pmix_item<PPL, W>(a, a.items[it], U, V, tab, slotseg, slotf, red, smem);
     if (!persistent) break;
     it = W == 1 ? next_item(a) : next_item_wg(a, &s_item);
   }
@@ -1634,7 +1711,7 @@ static size_t refine_lds_bytes(gp_kind kind, gp_precision prec, int ec, int W) {
     return prec == GP_FP64 ? (size_t)ec * sizeof(PipRec64) : (size_t)ec * (16 + 16 + 4);
   if (prec == GP_FP64) return (size_t)ec * (sizeof(SegRec64) + sizeof(int2));
   // the chunk (segment records, polyline table, slot map), reused by the exact pass
-  const size_t chunk = (size_t)ec * (16 + 4 + sizeof(int2) + sizeof(int));
+  const size_t chunk = (size_t)ec * (16 + 4 + sizeof(int2) + 2 * sizeof(int));
   const size_t epi = (size_t)W * P2P_EPI_BYTES;
   return chunk > epi ? chunk : epi;
 }

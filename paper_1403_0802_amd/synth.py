@@ -64,6 +64,7 @@ class GridParams:
     nx: int = 0  # 0: derive the extent from the (expanded) MBBs
     ny: int = 0
     cell_classes: int = 0  # PIP: 1 asks the GPU grid to classify cell/polygon pairs
+    segment_filter: int = 0  # P2P: 1 asks the GPU grid for per-cell segment lists
 
 
 @dataclasses.dataclass

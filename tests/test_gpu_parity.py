@@ -384,6 +384,70 @@ def test_results_invariant_under_cell_size(gp, c1, kind):
     assert all(tests[order[i]] <= tests[order[i + 1]] for i in range(len(sizes) - 1)), rows
 
 
+# ---------------------------------------------------------------- P2P segment filter
+
+
+@pytest.mark.parametrize("case", ["c2", "ties", "near", "c4"])
+def test_p2p_segment_filter_equal_unfiltered(gp, case):
+    """Per-cell segment lists (segments whose D-expanded box reaches the cell) give the
+    oracle's ids and distances bit for bit in the mixed form, perform exactly the
+    unfiltered tests minus the avoided ones, and leave the FP64 form unchanged."""
+    say("p2p segment filter", case)
+    rng = np.random.default_rng(17)
+    if case == "c2":
+        w = synth.config2(n_points=300_000, n_lines=6_000, seed_salt=7)
+        g, params, px, py = w.geom, w.params, w.px, w.py
+    elif case == "ties":
+        lines = [[(0.0, 2.0), (10.0, 2.0)], [(0.0, -2.0), (10.0, -2.0)], [(0.0, 5.0), (10.0, 5.0)],
+                 [(3.0, 3.0), (3.0, 3.0), (4.0, 3.5)], [(20.0, 20.0)] * 3]
+        t = np.linspace(0, 1, 1501)
+        lines.append(list(zip(30 + 10 * np.cos(6 * t), 30 + 10 * np.sin(6 * t))))
+        g = pins.polylines(lines)
+        params = synth.GridParams(cell_size=1.0, radius_D=2.0, x0=-10, y0=-10, nx=64, ny=64)
+        px = np.concatenate([[5.0, 5.0, 5.0, 5.0, 20.0, 22.0, 3.0], rng.uniform(-8, 50, 100_000)])
+        py = np.concatenate([[0.0, 3.0, 7.0, np.nextafter(-4.0, -5.0), 20.0, 20.0, 1.0],
+                             rng.uniform(-8, 50, 100_000)])
+    elif case == "near":
+        w = synth.config2(n_points=10, n_lines=3_000, seed_salt=6)
+        g, params = w.geom, w.params
+        D = params.radius_D
+        x, y, rvo = g.x, g.y, g.ring_vert_off
+        seg = np.concatenate([np.arange(rvo[f], rvo[f + 1] - 1) for f in range(g.n_features)])
+        k = rng.choice(seg, 200_000)
+        s_ = rng.uniform(0, 1, len(k))
+        ex, ey = x[k + 1] - x[k], y[k + 1] - y[k]
+        L = np.hypot(ex, ey) + 1e-300
+        off = D + 10.0 ** rng.uniform(-9, -3, len(k)) * rng.choice([-1, 1], len(k))
+        px = x[k] + s_ * ex - ey / L * off
+        py = y[k] + s_ * ey + ex / L * off
+    else:
+        g = synth.config4_geometry(n_lines=200_000)
+        params = synth.GridParams(cell_size=100.0, radius_D=100.0, nx=400, ny=400)
+        px, py = synth.config4_points(4_000_000, seed_salt=2)
+    og = oracle.build_grid(g, params)
+    if case == "c4":
+        sel = rng.choice(len(px), 20_000, replace=False)
+        want_id, want_d = oracle.p2p(g, px[sel], py[sel], params.radius_D, og)
+    else:
+        want_id, want_d = oracle.p2p(g, px, py, params.radius_D, og)
+    plain = gp.gp_build_grid("p2p", g, params)
+    filt = gp.gp_build_grid("p2p", g, synth.GridParams(**{**params.__dict__, "segment_filter": 1}))
+    assert filt.info()["n_segment_pairs"] > 0
+    for prec in ("fp64", "mixed"):
+        r0 = run_gpu(gp, plain, px, py, prec, stats=True)
+        r1 = run_gpu(gp, filt, px, py, prec, stats=True)
+        assert np.array_equal(r1[0], r0[0]) and np.array_equal(r1[1], r0[1]), (case, prec)
+        gid, gd = (r1[0][sel], r1[1][sel]) if case == "c4" else (r1[0], r1[1])
+        check_p2p(gid, gd, want_id, want_d, prec, f"{case} {prec}")
+        st0, st1 = r0[2], r1[2]
+        if prec == "mixed":
+            assert st1["tests"] + st1["tests_avoided"] == st0["tests"]
+            assert st1["tests"] < st0["tests"]
+        else:
+            assert st1["tests"] == st0["tests"] and st1["tests_avoided"] == 0
+        say("  ", prec, "tests", st1["tests"], "avoided", st1["tests_avoided"])
+
+
 def test_near_edge_sweep_mixed(gp):
     """Points at distances 1e-15 .. 1e-3 (relative to the unit square) from polygon
     edges, on both sides: the guard band must send every doubtful one to FP64."""
