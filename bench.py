@@ -337,6 +337,19 @@ def main():
         log("[bench] autotune p2p on", sx.numel(), "points",
             gp.gp_autotune(grid4, prec, sx, sy, ws4))
         del sx, sy
+        # the sample's winner must also beat the library default on the full workload
+        # (configurations within noise of each other can swap places at full size)
+        for grid, run1 in ((grid3, lambda: gp.gp_pip(grid3, x3, y3, id3, prec, ws3, stream, True)),
+                           (grid4, lambda: gp.gp_p2p(grid4, x4, y4, id4, d4, prec, ws4, stream, True))):
+            tuned = gp.gp_get_tuning(grid, prec)
+            t_tuned = min(run1()["ms_total"] for _ in range(2))
+            gp.gp_reset_tuning(grid, prec)
+            default = gp.gp_get_tuning(grid, prec)
+            t_default = min(run1()["ms_total"] for _ in range(2))
+            if t_tuned < t_default:
+                gp.gp_set_tuning(grid, prec, **tuned)
+            log("[bench] full-size check: tuned %.2f ms, default %.2f ms -> %s" % (
+                t_tuned, t_default, gp.gp_get_tuning(grid, prec)))
 
     def step(stats):
         a = gp.gp_pip(grid3, x3, y3, id3, prec, ws3, stream, stats)
@@ -423,6 +436,30 @@ def main():
                       "boundary": info["n_pairs_boundary"]},
             "grid_build_ms": build_c}
         del grid3c, id3c
+    # P2P with per-cell segment lists: segments that cannot come within D of a cell are
+    # never tested; same ids and distances (reported apart from the headline)
+    if not args.no_classes:
+        from paper_1403_0802_amd import synth
+        p4f = synth.GridParams(**{**p4.__dict__, "segment_filter": 1})
+        t0 = time.perf_counter()
+        grid4f = gp.gp_build_grid("p2p", geom4, p4f)
+        build_f = 1e3 * (time.perf_counter() - t0)
+        tune = gp.gp_get_tuning(grid4, prec)
+        gp.gp_set_tuning(grid4f, prec, **{k: tune[k] for k in tune})
+        id4f = torch.empty_like(id4)
+        d4f = torch.empty_like(d4)
+        gp.gp_p2p(grid4f, x4, y4, id4f, d4f, prec, ws4, stream, False)
+        stf = [gp.gp_p2p(grid4f, x4, y4, id4f, d4f, prec, ws4, stream, True) for _ in range(3)]
+        info = grid4f.info()
+        detail["p2p_segment_filter"] = {
+            "ms": avg(stf, "ms_total"), "ms_refine": avg(stf, "ms_refine"),
+            "ms_without": avg(st_p2p, "ms_total"), "tests": stf[0]["tests"],
+            "tests_avoided": stf[0]["tests_avoided"],
+            "refine_tests_per_s": stf[0]["tests"] / (avg(stf, "ms_refine") / 1e3),
+            "same_as_unfiltered": bool(torch.equal(id4f, id4) and torch.equal(d4f, d4)),
+            "segment_pairs": info["n_segment_pairs"], "grid_bytes": info["device_bytes"],
+            "grid_build_ms": build_f}
+        del grid4f, id4f, d4f
     # the FP64 form on the same inputs, for comparison
     if not args.no_fp64:
         del ws3, ws4

@@ -199,7 +199,8 @@ gp_status gp_p2p(const gp_grid *grid, int64_t n, const double *px, const double 
                  int32_t *out_id, double *out_dist, gp_precision prec, void *ws,
                  size_t ws_bytes, void *hip_stream, gp_stats *stats);
 
-/* Kernel configuration of a grid for one precision form. */
+/* Kernel configuration of a grid for one precision form.  gp_set_tuning with a NULL
+ * tuning restores the library default. */
 gp_status gp_set_tuning(gp_grid *grid, gp_precision prec, const gp_tuning *tuning);
 gp_status gp_get_tuning(const gp_grid *grid, gp_precision prec, gp_tuning *tuning);
 

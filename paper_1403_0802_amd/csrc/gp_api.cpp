@@ -692,8 +692,12 @@ extern "C" gp_status gp_p2p(const gp_grid *g, int64_t n, const double *px, const
 // ------------------------------------------------------------------------- tuning
 
 extern "C" gp_status gp_set_tuning(gp_grid *g, gp_precision prec, const gp_tuning *t) {
-  if (!g || !t) return set_error(GP_E_INVALID_ARG, "null argument");
+  if (!g) return set_error(GP_E_INVALID_ARG, "null argument");
   if (prec != GP_FP64 && prec != GP_MIXED) return set_error(GP_E_INVALID_ARG, "bad precision");
+  if (!t) {  // back to the library default
+    g->tune[prec] = default_tuning(g->kind, prec);
+    return GP_OK;
+  }
   gp_tuning v = *t;
   gp_tuning d = default_tuning(g->kind, prec);
   if (v.points_per_lane == 0) v.points_per_lane = d.points_per_lane;

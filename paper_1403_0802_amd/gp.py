@@ -252,6 +252,11 @@ def gp_set_tuning(grid, prec, points_per_lane=0, edge_chunk=0, wg_per_cu=0, pers
     check(lib.gp_set_tuning(grid.handle, PRECISIONS.get(prec, prec), ctypes.byref(t)))
 
 
+def gp_reset_tuning(grid, prec):
+    """Restore the library's default kernel configuration (gp_set_tuning with NULL)."""
+    check(lib.gp_set_tuning(grid.handle, PRECISIONS.get(prec, prec), None))
+
+
 def gp_get_tuning(grid, prec) -> dict:
     t = gp_tuning()
     check(lib.gp_get_tuning(grid.handle, PRECISIONS.get(prec, prec), ctypes.byref(t)))

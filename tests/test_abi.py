@@ -69,6 +69,7 @@ def test_argument_errors_are_synchronous():
     assert L.gp_serve_create(None, None, ctypes.byref(opts), ctypes.byref(out)) == gp.GP_E_INVALID_ARG
     assert L.gp_serve_destroy(None) == gp.GP_E_INVALID_ARG
     assert L.gp_set_tuning(None, 0, None) == gp.GP_E_INVALID_ARG
+    assert L.gp_set_tuning(None, 0, ctypes.byref(gp.gp_tuning())) == gp.GP_E_INVALID_ARG
 
 
 def test_oracle_and_gpu_path_share_no_code():

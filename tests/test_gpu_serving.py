@@ -141,3 +141,5 @@ def test_autotune_keeps_results(setup):
     assert gp.gp_get_tuning(g3, "mixed") == best
     r = gp.run(g3, x, y, "mixed")
     assert torch.equal(r.cpu(), alone[0][0].cpu())
+    gp.gp_reset_tuning(g3, "mixed")
+    assert gp.gp_get_tuning(g3, "mixed")["vp_points"] == 16
