@@ -30,7 +30,7 @@ namespace gp {
 #define SCAN_ITEMS 16
 #define SCAN_TILE (SCAN_THREADS * SCAN_ITEMS)
 #define RS_THREADS 256
-#define RS_ITEMS 16
+#define RS_ITEMS 8
 #define RS_TILE (RS_THREADS * RS_ITEMS)
 #define RS_MAX_BITS 10
 #define RS_MAX_BUCKETS (1 << RS_MAX_BITS)
@@ -206,42 +206,85 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t *keys, si
 
 // Payload: pass 0 reads it from the caller's separate x/y arrays (px0, py0), later
 // passes from the interleaved array pin; it is written interleaved to pout.
+//
+// Each tile is first sorted by digit in LDS (stable: records are ranked in input order,
+// round by round, wave by wave, lane by lane, with ballot peer masks), then written out
+// in that order, so consecutive threads store consecutive records of one digit: the
+// global writes form runs instead of single scattered records.
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, size_t n,
     int shift, int bits, const uint32_t *offs, uint32_t nblk, const double *px0,
     const double *py0, const double2 *pin, double2 *pout) {
-  __shared__ uint32_t run[RS_MAX_BUCKETS];
-  __shared__ uint32_t wcnt[RS_THREADS / GP_WAVE][RS_MAX_BUCKETS];
+  __shared__ uint32_t sk[RS_TILE], sv[RS_TILE];
+  __shared__ double2 sp[RS_TILE];
+  __shared__ uint32_t lpos[RS_MAX_BUCKETS];  // histogram, then next free local slot
+  __shared__ uint32_t delta[RS_MAX_BUCKETS]; // global start - local start of each digit
+  __shared__ uint8_t wcnt[RS_THREADS / GP_WAVE][RS_MAX_BUCKETS];
   const uint32_t tid = threadIdx.x, wave = tid / GP_WAVE;
   const uint32_t nb = 1u << bits, mask = nb - 1u;
-  for (uint32_t d = tid; d < nb; d += RS_THREADS) {
-    run[d] = offs[(size_t)d * nblk + blockIdx.x];
+  const size_t base = (size_t)blockIdx.x * RS_TILE;
+  const int tn = (int)((n - base) < (size_t)RS_TILE ? (n - base) : (size_t)RS_TILE);
+  for (uint32_t d = tid; d < RS_MAX_BUCKETS; d += RS_THREADS) {
+    lpos[d] = 0;
     for (int w = 0; w < RS_THREADS / GP_WAVE; ++w) wcnt[w][d] = 0;
   }
   __syncthreads();
-  const size_t base = (size_t)blockIdx.x * RS_TILE;
+  // the tile's records, in registers; local digit histogram
+  uint32_t k[RS_ITEMS], v[RS_ITEMS];
+  double2 pl[RS_ITEMS];
+#pragma unroll
   for (int r = 0; r < RS_ITEMS; ++r) {
-    size_t i = base + (size_t)r * RS_THREADS + tid;
-    bool valid = i < n;
-    uint32_t k = valid ? kin[i] : 0u;
-    uint32_t v = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
-    double2 pl = make_double2(0.0, 0.0);
-    if (valid && pout) pl = pin ? pin[i] : make_double2(px0[i], py0[i]);
-    uint32_t d = (k >> shift) & mask;
+    const int li = r * RS_THREADS + (int)tid;
+    const size_t i = base + (size_t)li;
+    const bool valid = li < tn;
+    k[r] = valid ? kin[i] : 0u;
+    v[r] = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
+    pl[r] = make_double2(0.0, 0.0);
+    if (valid && pout) pl[r] = pin ? pin[i] : make_double2(px0[i], py0[i]);
+    if (valid) atomicAdd(&lpos[(k[r] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  // exclusive scan of the histogram: thread t owns digits 4t .. 4t+3
+  {
+    uint32_t c[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t d = 4 * tid + q;
+      c[q] = d < nb ? lpos[d] : 0u;
+      sum += c[q];
+    }
+    uint32_t tot;
+    uint32_t pre = block_excl_scan(sum, &tot);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t d = 4 * tid + q;
+      if (d < nb) {
+        lpos[d] = pre;
+        delta[d] = offs[(size_t)d * nblk + blockIdx.x] - pre;
+      }
+      pre += c[q];
+    }
+  }
+  __syncthreads();
+  // stable ranking into LDS
+#pragma unroll
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    const bool valid = r * RS_THREADS + (int)tid < tn;
+    const uint32_t d = (k[r] >> shift) & mask;
     uint64_t peers = ballot(valid);
     for (int b = 0; b < bits; ++b) {
-      uint64_t m = ballot((d >> b) & 1u);
+      const uint64_t m = ballot((d >> b) & 1u);
       peers &= ((d >> b) & 1u) ? m : ~m;
     }
-    uint32_t rank = __popcll(peers & lanemask_lt());
-    if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
+    const uint32_t rank = __popcll(peers & lanemask_lt());
+    if (valid && rank == 0) wcnt[wave][d] = (uint8_t)__popcll(peers);
     __syncthreads();
     if (valid) {
-      uint32_t pos = run[d] + rank;
+      uint32_t pos = lpos[d] + rank;
       for (uint32_t w = 0; w < wave; ++w) pos += wcnt[w][d];
-      kout[pos] = k;
-      vout[pos] = v;
-      if (pout) pout[pos] = pl;
+      sk[pos] = k[r];
+      sv[pos] = v[r];
+      if (pout) sp[pos] = pl[r];
     }
     __syncthreads();
     for (uint32_t dd = tid; dd < nb; dd += RS_THREADS) {
@@ -250,9 +293,17 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
         add += wcnt[w][dd];
         wcnt[w][dd] = 0;
       }
-      run[dd] += add;
+      lpos[dd] += add;
     }
     __syncthreads();
+  }
+  // write out in local order: global slot = local slot + (global - local start) of the digit
+  for (int j = (int)tid; j < tn; j += RS_THREADS) {
+    const uint32_t key = sk[j];
+    const uint32_t gpos = delta[(key >> shift) & mask] + (uint32_t)j;
+    kout[gpos] = key;
+    vout[gpos] = sv[j];
+    if (pout) pout[gpos] = sp[j];
   }
 }
 
