@@ -634,3 +634,53 @@ def test_c4_scaled_mixed_vs_oracle_sample(gp):
     wid, wd = oracle.p2p(geom, px[idx], py[idx], 100.0, og)
     check_p2p(i64[idx], d64[idx], wid, wd, "fp64", "c4 sample")
     say("  fp64", s64, "\n  mixed", smx, "\n  max err", err.max())
+
+
+# ---------------------------------------------------------------- full sizes
+
+
+def _device_run(gp, grid, x, y, prec):
+    r = gp.run(grid, x, y, prec, stats=True)
+    torch.cuda.synchronize()
+    return r
+
+
+def test_c3_full_size_50m(gp, c3_geom):
+    """Configuration 3 at its full 50M points, default launch configuration: the mixed
+    ids equal the FP64 ids on every point (compared on the device), and 20,000 sampled
+    points equal the oracle."""
+    geom, _ = c3_geom
+    say("c3 full size: 50M points")
+    px, py = synth.config3_points(50_000_000)
+    params = synth.GridParams(cell_size=1 / 1024, nx=1024, ny=1024)
+    grid = gp.gp_build_grid("pip", geom, params)
+    x, y = dev_arrays(px, py)
+    g64, s64 = _device_run(gp, grid, x, y, "fp64")
+    gmx, smx = _device_run(gp, grid, x, y, "mixed")
+    assert torch.equal(g64, gmx), int((g64 != gmx).sum())
+    idx = np.random.default_rng(30).choice(len(px), 20_000, replace=False)
+    want = oracle.pip(geom, px[idx], py[idx], oracle.build_grid(geom, params))
+    assert np.array_equal(gmx.cpu().numpy()[idx], want)
+    assert smx["tests"] == s64["tests"] == 28_869_883_377
+    say("  mixed", smx)
+
+
+def test_c4_full_size_200m(gp):
+    """Configuration 4 at its full 200M points, default launch configuration: mixed ids
+    and distances equal the FP64 form's on every point (compared on the device), and
+    20,000 sampled points equal the oracle."""
+    say("c4 full size: 200M points")
+    geom = synth.config4_geometry()
+    px, py = synth.config4_points(200_000_000)
+    params = synth.GridParams(cell_size=100.0, radius_D=100.0, nx=400, ny=400)
+    grid = gp.gp_build_grid("p2p", geom, params)
+    x, y = dev_arrays(px, py)
+    i64, d64, s64 = _device_run(gp, grid, x, y, "fp64")
+    imx, dmx, smx = _device_run(gp, grid, x, y, "mixed")
+    assert torch.equal(i64, imx), int((i64 != imx).sum())
+    assert torch.equal(d64, dmx)
+    idx = np.random.default_rng(31).choice(len(px), 20_000, replace=False)
+    wid, wd = oracle.p2p(geom, px[idx], py[idx], 100.0, oracle.build_grid(geom, params))
+    check_p2p(imx.cpu().numpy()[idx], dmx.cpu().numpy()[idx], wid, wd, "mixed", "c4 full sample")
+    assert smx["tests"] == s64["tests"] == 1_099_498_435_953
+    say("  mixed", smx)
