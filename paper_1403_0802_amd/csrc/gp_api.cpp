@@ -148,7 +148,10 @@ extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
 
   HostGeom h;
   GP_TRY_HIP(fetch(h.rvo, geom->ring_vert_off, (size_t)nr + 1, dev));
-  if (kind == GP_PIP) GP_TRY_HIP(fetch(h.fro, geom->feature_ring_off, (size_t)nf + 1, dev));
+  if (kind == GP_PIP && geom->feature_ring_off)
+    GP_TRY_HIP(fetch(h.fro, geom->feature_ring_off, (size_t)nf + 1, dev));
+  else if (kind == GP_PIP)
+    h.fro.assign(1, 0);  // no polygons: the offsets are the single 0
   GP_TRY_HIP(fetch(h.x, geom->x, (size_t)nv, dev));
   GP_TRY_HIP(fetch(h.y, geom->y, (size_t)nv, dev));
   gp_status st = check_offsets(h.rvo, nv, "ring_vert_off");

@@ -220,6 +220,17 @@ def test_empty_and_unpaired_inputs(gp):
     for prec in ("fp64", "mixed"):
         gid, gd = run_gpu(gp, g2, px * 1e5, py * 1e5, prec)
         assert np.all(gid == -1) and np.all(np.isinf(gd))
+    # feature sets without features: every point is unpaired
+    z = np.zeros(0)
+    for kind, geom in (("pip", synth.Geometry("pip", np.zeros(1, np.int64), z, z, None)),
+                       ("pip", synth.Geometry("pip", np.zeros(1, np.int64), z, z,
+                                              np.zeros(1, np.int64))),
+                       ("p2p", synth.Geometry("p2p", np.zeros(1, np.int64), z, z, None))):
+        params = synth.GridParams(cell_size=0.25, radius_D=0.1, nx=4, ny=4)
+        grid = gp.gp_build_grid(kind, geom, params)
+        for prec in ("fp64", "mixed"):
+            r = run_gpu(gp, grid, px * 0 + 0.5, py * 0 + 0.5, prec)
+            assert np.all((r if kind == "pip" else r[0]) == -1)
 
 
 def test_points_on_vertices_edges_and_vertex_heights(gp):
