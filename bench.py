@@ -484,6 +484,15 @@ def main():
         del x4, y4, id4, d4
         torch.cuda.empty_cache()
         detail["serving"] = serving_run(gp, torch, grid3, grid4, args.serve_requests, prec)
+        if not args.no_classes:
+            # the same stream against grids built with the work filters (PIP cell classes,
+            # P2P segment lists): identical results, less work per request
+            from paper_1403_0802_amd import synth
+            g3f = gp.gp_build_grid("pip", geom3, synth.GridParams(**{**p3.__dict__, "cell_classes": 1}))
+            g4f = gp.gp_build_grid("p2p", geom4, synth.GridParams(**{**p4.__dict__, "segment_filter": 1}))
+            detail["serving_filtered_grids"] = serving_run(gp, torch, g3f, g4f,
+                                                           args.serve_requests, prec)
+            del g3f, g4f
     out = {
         "metric": METRIC,
         "value": value,

@@ -32,7 +32,7 @@ namespace gp {
 #define RS_THREADS 256
 #define RS_ITEMS 8
 #define RS_TILE (RS_THREADS * RS_ITEMS)
-#define RS_MAX_BITS 10
+#define RS_MAX_BITS 8
 #define RS_MAX_BUCKETS (1 << RS_MAX_BITS)
 
 __device__ __forceinline__ uint64_t ballot(bool c) { return __builtin_amdgcn_ballot_w64(c); }

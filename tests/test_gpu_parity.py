@@ -229,7 +229,7 @@ def test_empty_and_unpaired_inputs(gp):
         params = synth.GridParams(cell_size=0.25, radius_D=0.1, nx=4, ny=4)
         grid = gp.gp_build_grid(kind, geom, params)
         for prec in ("fp64", "mixed"):
-            r = run_gpu(gp, grid, px * 0 + 0.5, py * 0 + 0.5, prec)
+            r = run_gpu(gp, grid, np.full_like(px, 0.5), np.full_like(py, 0.5), prec)
             assert np.all((r if kind == "pip" else r[0]) == -1)
 
 
