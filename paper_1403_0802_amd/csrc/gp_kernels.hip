@@ -1408,6 +1408,7 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
     f2[j] = -1;
   }
   float emax = 0.0f;  // per-thread partial of E over the segments this thread staged
+  float eall = 0.0f;  // the same over every staged segment, near the cell or not
   // Stage one segment into chunk slot t: its frame constants relative to the cell centre
   // c (s_c = -(m - c).u, r_c = -(m - c).v, scaled), and its share of the error bound E.
   auto stage = [&](int t, const double4 F, const float4 G) {
@@ -1424,6 +1425,7 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
     const float ex = fmaxf(0.0f, fs - 0.5f * G.w);
     const bool nearc = !(ex * ex + fr * fr > near_lim2) || !(es <= 0.5f * T);
     if (nearc) emax = fmaxf(emax, es);
+    eall = fmaxf(eall, es);
   };
   // With a segment filter the cell's chunks are slices of its list of reaching segments;
   // otherwise they are cut from its candidate polylines' whole segment ranges.
@@ -1548,11 +1550,20 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
     }
   }
   // E = maximum over the whole workgroup's staged segments
-  for (int off = 32; off > 0; off >>= 1) emax = fmaxf(emax, __shfl_xor(emax, off, GP_WAVE));
+  for (int off = 32; off > 0; off >>= 1) {
+    emax = fmaxf(emax, __shfl_xor(emax, off, GP_WAVE));
+    eall = fmaxf(eall, __shfl_xor(eall, off, GP_WAVE));
+  }
   if (W > 1) {
-    if (lane == 0) red[wave] = emax;
+    if (lane == 0) {
+      red[wave] = emax;
+      red[4 + wave] = eall;
+    }
     __syncthreads();
-    for (int w = 0; w < W; ++w) emax = fmaxf(emax, red[w]);
+    for (int w = 0; w < W; ++w) {
+      emax = fmaxf(emax, red[w]);
+      eall = fmaxf(eall, red[4 + w]);
+    }
     __syncthreads();
   }
   if (!wave_live) return;
@@ -1560,14 +1571,14 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
   const double D = a.D;
   // Exact FP64 distances of each point's one or two candidate polylines.  With d_c the
   // FP32-derived distance of candidate c, the exact minimum over its segments is at most
-  // d_c + E' with E' = max(E, T/2): every staged segment's error is at most E (near the
-  // cell) or T/2 (otherwise it would count as near).  A block of P2P_BLOCK segments
-  // whose bounding circle lies farther than d_c + E' cannot hold the minimum.  The wave tests the blocks of all its (point, polyline) pairs
-  // together, queues the blocks that pass in LDS, and evaluates them 64 at a time, one
-  // per lane; each block's minimum joins its pair's result by an LDS atomic minimum.
-  // Non-negative doubles order like their bit patterns, so the result is the exact
-  // minimum over the polyline's segments whatever the order of the blocks.
-  const double Ep = fmax(E, 0.5 * (double)T);
+  // d_c + E', E' the largest error bound of any staged segment (its FP32-best segment
+  // is one of them).  A block of P2P_BLOCK segments whose bounding circle lies farther
+  // than d_c + E' cannot hold the minimum.  The wave tests the blocks of all its
+  // (point, polyline) pairs together, queues the blocks that pass in LDS, and evaluates
+  // them 64 at a time, one per lane; each block's minimum joins its pair's result by an
+  // LDS atomic minimum.  Non-negative doubles order like their bit patterns, so the
+  // result is the exact minimum over the polyline's segments whatever the order.
+  const double Ep = (double)eall;
   wave_lds_sync();  // with one wave per item the chunk's LDS is reused without a barrier
   unsigned char *wepi = epi + wave * P2P_EPI_BYTES;
   uint64_t *res = (uint64_t *)wepi;                  // [2*64] result bits per pair
@@ -1742,7 +1753,7 @@ template <int PPL, int W>
 __global__ __launch_bounds__(64 * W) void k_p2pmix(RefineArgs a, int persistent) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t s_item;
-  __shared__ float red[4];
+  __shared__ float red[8];
   float4 *U = (float4 *)smem;
   float *V = (float *)(U + a.edge_chunk);
   int2 *tab = (int2 *)(V + a.edge_chunk);
