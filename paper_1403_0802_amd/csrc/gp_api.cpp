@@ -551,6 +551,9 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   if (n == 0) return GP_OK;
   if (!px || !py || !out_id || (kind == GP_P2P && !out_dist))
     return set_error(GP_E_INVALID_ARG, "null point or output pointer");
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess || cur != g->device)
+    return set_error(GP_E_INVALID_ARG, "the grid lives on device %d; make it current", g->device);
   Workspace w;
   const size_t need = workspace_layout(*g, n, prec, ws, &w);
   if (!ws || ws_bytes < need)

@@ -187,6 +187,9 @@ static void complete(gp_server *srv, Slot &sl, gp_status st) {
 }
 
 static void server_loop(gp_server *srv) {
+  // the device the grids live on (a new host thread starts on device 0)
+  const gp_grid *g0 = srv->grid[GP_PIP] ? srv->grid[GP_PIP] : srv->grid[GP_P2P];
+  (void)hipSetDevice(((const Grid *)g0)->device);
   for (;;) {
     bool busy = false;
     // completions
