@@ -602,6 +602,29 @@ def test_bad_geometry_is_rejected(gp):
     assert e.value.status == gp.GP_E_BAD_GEOMETRY
 
 
+def test_grid_and_option_limits(gp):
+    """Grids above 2^28 cells (explicit or derived) and bad option values are refused;
+    a workspace that is too small is refused before any launch."""
+    g = pins.polygons([[pins.box(0.0, 0.0, 1.0, 1.0)]])
+    for params in (synth.GridParams(cell_size=1e-5, nx=1 << 15, ny=1 << 15),
+                   synth.GridParams(cell_size=1e-6)):
+        with pytest.raises(gp.GPError) as e:
+            gp.gp_build_grid("pip", g, params)
+        assert e.value.status == gp.GP_E_CAPACITY, params
+    with pytest.raises(gp.GPError) as e:
+        gp.gp_build_grid("pip", g, synth.GridParams(cell_size=0.5, cell_classes=2))
+    assert e.value.status == gp.GP_E_INVALID_ARG
+    grid = gp.gp_build_grid("pip", g, synth.GridParams(cell_size=0.5))
+    x = torch.full((1000,), 0.5, dtype=torch.float64, device="cuda")
+    ws = gp.new_workspace(grid, 10, "mixed")
+    with pytest.raises(gp.GPError) as e:
+        gp.gp_pip(grid, x, x, torch.empty(1000, dtype=torch.int32, device="cuda"), "mixed", ws)
+    assert e.value.status == gp.GP_E_INVALID_ARG
+    with pytest.raises(gp.GPError) as e:
+        gp.gp_set_tuning(grid, "mixed", points_per_lane=3)
+    assert e.value.status == gp.GP_E_INVALID_ARG
+
+
 # ---------------------------------------------------------------------------- scale
 
 
