@@ -267,7 +267,7 @@ def main():
     ap.add_argument("--no-cpu-simd", action="store_true",
                     help="skip the host SIMD/multi-core implementation's four modes")
     ap.add_argument("--no-classes", action="store_true",
-                    help="skip the PIP cell-classification measurement")
+                    help="skip the grid-option measurements (cell classes, segment filter, prestage)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--cell-sweep", action="store_true",
@@ -460,6 +460,28 @@ def main():
             "segment_pairs": info["n_segment_pairs"], "grid_bytes": info["device_bytes"],
             "grid_build_ms": build_f}
         del grid4f, id4f, d4f
+    # P2P with build-time segment records: every cell's mixed-form records (20 bytes per
+    # cell/segment pair) are computed once with the resident grid; same tests, same
+    # results (reported apart from the headline)
+    if not args.no_classes:
+        from paper_1403_0802_amd import synth
+        p4p = synth.GridParams(**{**p4.__dict__, "prestage": 1})
+        t0 = time.perf_counter()
+        grid4p = gp.gp_build_grid("p2p", geom4, p4p)
+        build_p = 1e3 * (time.perf_counter() - t0)
+        tune = gp.gp_get_tuning(grid4, prec)
+        gp.gp_set_tuning(grid4p, prec, **{k: tune[k] for k in tune})
+        id4p = torch.empty_like(id4)
+        d4p = torch.empty_like(d4)
+        gp.gp_p2p(grid4p, x4, y4, id4p, d4p, prec, ws4, stream, False)
+        stp = [gp.gp_p2p(grid4p, x4, y4, id4p, d4p, prec, ws4, stream, True) for _ in range(3)]
+        detail["p2p_prestage"] = {
+            "ms": avg(stp, "ms_total"), "ms_refine": avg(stp, "ms_refine"),
+            "ms_refine_without": avg(st_p2p, "ms_refine"), "tests": stp[0]["tests"],
+            "refine_tests_per_s": stp[0]["tests"] / (avg(stp, "ms_refine") / 1e3),
+            "same_as_plain": bool(torch.equal(id4p, id4) and torch.equal(d4p, d4)),
+            "grid_bytes": grid4p.info()["device_bytes"], "grid_build_ms": build_p}
+        del grid4p, id4p, d4p
     # the FP64 form on the same inputs, for comparison
     if not args.no_fp64:
         del ws3, ws4

@@ -110,7 +110,12 @@ typedef struct gp_geometry {
  * segments it reaches; the GP_MIXED form then tests only those (a segment farther than
  * D from the whole cell can neither be a point's nearest segment within range nor bring
  * a polyline into range), with the same results; tests and tests_avoided as above.  The
- * GP_FP64 form keeps testing every candidate segment. */
+ * GP_FP64 form keeps testing every candidate segment.
+ * p2p_prestage = 1 (P2P only; 0 otherwise; ignored with p2p_segment_filter) computes at
+ * build time, for every cell, the cell-relative FP32 records of all its candidate
+ * segments and the cell's error bounds, which GP_MIXED queries then read instead of
+ * computing them per work item: 20 bytes per (cell, candidate segment), reported in
+ * gp_grid_info.device_bytes.  Same results. */
 typedef struct gp_grid_params {
     double cell_size;
     double radius_D;
@@ -118,6 +123,7 @@ typedef struct gp_grid_params {
     int64_t nx, ny;
     int32_t pip_cell_classes;
     int32_t p2p_segment_filter;
+    int32_t p2p_prestage;
 } gp_grid_params;
 
 typedef struct gp_grid gp_grid;

@@ -113,6 +113,18 @@ static gp_status check_offsets(const std::vector<int64_t> &off, int64_t end, con
 
 // ------------------------------------------------------------------------- grid build
 
+// Half the side of a cell, rounded up, plus the rounding of the FP32 cell-relative
+// coordinates: every point of a cell lies within this box around the cell centre.
+static float half_box(const Grid &g) {
+  double hb = 0.5 * g.cs * (1.0 + 0x1p-18) +
+              0x1p-48 * (std::fabs(g.x0) + std::fabs(g.y0) + g.cs * (double)(g.nx + g.ny));
+  return (float)(hb * (1.0 + 0x1p-20));
+}
+
+// FP32 margin T of the mixed P2P test: a polyline is kept while its FP32 distance is
+// within D + T.
+static float p2p_margin(const Grid &g) { return (float)std::max(0.01 * g.D, g.cs * 0x1p-10); }
+
 extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
                                    const gp_grid_params *params, void *hip_stream,
                                    gp_grid **out) {
@@ -130,6 +142,8 @@ extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
     return set_error(GP_E_INVALID_ARG, "pip_cell_classes must be 0 or 1");
   if (params->p2p_segment_filter != 0 && params->p2p_segment_filter != 1)
     return set_error(GP_E_INVALID_ARG, "p2p_segment_filter must be 0 or 1");
+  if (params->p2p_prestage != 0 && params->p2p_prestage != 1)
+    return set_error(GP_E_INVALID_ARG, "p2p_prestage must be 0 or 1");
   const bool derive = params->nx == 0 || params->ny == 0;
   if (!derive && (!std::isfinite(params->x0) || !std::isfinite(params->y0)))
     return set_error(GP_E_INVALID_ARG, "non-finite grid origin");
@@ -397,6 +411,28 @@ extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
     GP_TRY_HIP_G(launch_cell_counts(g->d_cseg_off, ncells, g->d_cell_segs, s));
     GP_TRY_HIP_G(hipStreamSynchronize(s));
   }
+  if (kind == GP_P2P && params->p2p_prestage && !params->p2p_segment_filter && nedges > 0) {
+    // every cell's segment records, in the order the refinement reads them, at offsets
+    // from the prefix sum of the cells' candidate segment counts
+    std::vector<int64_t> off((size_t)ncells + 1);
+    GP_TRY_HIP_G(hipMemcpyAsync(off.data() + 1, g->d_cell_edges, (size_t)ncells * 8,
+                                hipMemcpyDeviceToHost, s));
+    GP_TRY_HIP_G(hipStreamSynchronize(s));
+    off[0] = 0;
+    for (size_t c = 1; c <= (size_t)ncells; ++c) off[c] += off[c - 1];
+    g->nrec = off[(size_t)ncells];
+    const size_t nrec = (size_t)std::max<int64_t>(g->nrec, 1);
+    GP_TRY_HIP_G(hipMalloc(&g->d_rec_off, off.size() * 8));
+    GP_TRY_HIP_G(hipMalloc(&g->d_recU, nrec * sizeof(float4)));
+    GP_TRY_HIP_G(hipMalloc(&g->d_recV, nrec * sizeof(float)));
+    GP_TRY_HIP_G(hipMalloc(&g->d_cellE, (size_t)ncells * sizeof(float2)));
+    GP_TRY_HIP_G(hipMemcpyAsync(g->d_rec_off, off.data(), off.size() * 8, hipMemcpyHostToDevice, s));
+    GP_TRY_HIP_G(launch_prestage(g->d_cand_off, g->d_cand_id, g->d_eoff, g->d_frame64,
+                                 g->d_frame32, g->x0, g->y0, g->cs, g->nx, ncells, g->D,
+                                 half_box(*g), p2p_margin(*g), g->p2p_scale, g->d_rec_off,
+                                 g->d_recU, g->d_recV, g->d_cellE, s));
+    GP_TRY_HIP_G(hipStreamSynchronize(s));
+  }
 #undef GP_TRY_HIP_G
   *out = g;
   return GP_OK;
@@ -419,6 +455,10 @@ extern "C" void gp_grid_free(gp_grid *g) {
   (void)hipFree(g->d_cseg);
   (void)hipFree(g->d_seg2f);
   (void)hipFree(g->d_cell_segs);
+  (void)hipFree(g->d_rec_off);
+  (void)hipFree(g->d_recU);
+  (void)hipFree(g->d_recV);
+  (void)hipFree(g->d_cellE);
   delete g;
 }
 
@@ -430,6 +470,7 @@ static int64_t grid_device_bytes(const Grid &g) {
   if (g.kind == GP_P2P) b += ne * (32 + 16) + (ne + P2P_BLOCK - 1) / P2P_BLOCK * 32;
   if (g.d_cand_class) b += np + nc * 8;
   if (g.d_cseg_off) b += (nc + 1) * 4 + std::max<int64_t>(g.ncseg, 1) * 4 + ne * 4 + nc * 8;
+  if (g.d_recU) b += (nc + 1) * 8 + std::max<int64_t>(g.nrec, 1) * 20 + nc * 8;
   return b;
 }
 
@@ -519,12 +560,6 @@ struct QueryPlan {
   int32_t nbits;
 };
 
-static float half_box(const Grid &g) {
-  double hb = 0.5 * g.cs * (1.0 + 0x1p-18) +
-              0x1p-48 * (std::fabs(g.x0) + std::fabs(g.y0) + g.cs * (double)(g.nx + g.ny));
-  return (float)(hb * (1.0 + 0x1p-20));
-}
-
 // Hash, sort and offsets: the point side of the filter.  With xy != NULL the FP64
 // points travel through the sort and *xy receives them in sorted order.
 static hipError_t pair_points(const Grid &g, int64_t n, const double *px, const double *py,
@@ -590,6 +625,11 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   a.cseg_off = segf ? g->d_cseg_off : nullptr;
   a.cseg = segf ? g->d_cseg : nullptr;
   a.seg2f = segf ? g->d_seg2f : nullptr;
+  const bool pre = prec == GP_MIXED && !segf && g->d_recU != nullptr;
+  a.recU = pre ? g->d_recU : nullptr;
+  a.recV = pre ? g->d_recV : nullptr;
+  a.rec_off = pre ? g->d_rec_off : nullptr;
+  a.cellE = pre ? g->d_cellE : nullptr;
   a.x0 = g->x0;
   a.y0 = g->y0;
   a.cs = g->cs;
@@ -599,7 +639,7 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   a.D2 = g->D2;
   a.D2_next = std::nextafter(g->D2, INFINITY);
   a.half_box = half_box(*g);
-  a.p2p_margin = (float)std::max(0.01 * g->D, g->cs * 0x1p-10);
+  a.p2p_margin = p2p_margin(*g);
   a.p2p_scale = g->p2p_scale;
   a.skey = skey;
   a.perm = perm;

@@ -42,6 +42,10 @@ struct RefineArgs {
   const int32_t *cseg_off;   // P2P mixed, optional: [ncells+1] into cseg
   const int32_t *cseg;       // the segments that reach each cell, ascending
   const int32_t *seg2f;      // [nseg] polyline of each segment
+  const float4 *recU;        // P2P mixed, optional build-time staging: per (cell, segment)
+  const float *recV;         //   records in refinement order, from rec_off[cell]
+  const int64_t *rec_off;    //   [ncells+1]
+  const float2 *cellE;       //   [ncells] E over near segments, E over all
   double x0, y0, cs;
   int32_t nx, ncells;
   double D, D2, D2_next;     // P2P: D, fl(D*D), the smallest double above fl(D*D)
@@ -86,6 +90,11 @@ struct Grid {
   int32_t *d_seg2f;       // [nedges]
   int64_t *d_cell_segs;   // [ncells] segments per cell
   int64_t ncseg;
+  float4 *d_recU;         // P2P build-time staging (p2p_prestage)
+  float *d_recV;
+  int64_t *d_rec_off;
+  float2 *d_cellE;
+  int64_t nrec;
   float p2p_scale;        // see RefineArgs
   gp_tuning tune[2];
   int num_cu;
@@ -147,6 +156,11 @@ hipError_t launch_histogram(const uint32_t *keys, size_t n, uint32_t *cnt, hipSt
 hipError_t launch_cell_edges(const int32_t *cand_off, const int32_t *cand_id,
                              const int32_t *eoff, const uint8_t *cand_class, int32_t ncells,
                              int64_t *cell_edges, hipStream_t s);
+hipError_t launch_prestage(const int32_t *cand_off, const int32_t *cand_id, const int32_t *eoff,
+                           const double4 *frame64, const float4 *frame32, double x0, double y0,
+                           double cs, int32_t nx, int32_t ncells, double D, float hb, float T,
+                           float sc, const int64_t *rec_off, float4 *recU, float *recV,
+                           float2 *cellE, hipStream_t s);
 hipError_t launch_seg_boxes(const double4 *seg64, int32_t nseg, double D, double pad,
                             double *box, hipStream_t s);
 hipError_t launch_seg2f(const int32_t *eoff, int32_t nf, int32_t *seg2f, hipStream_t s);

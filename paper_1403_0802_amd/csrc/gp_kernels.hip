@@ -1371,6 +1371,101 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// One segment's record for a cell with centre c: its frame constants relative to c
+// (s_c = -(m - c).u, r_c = -(m - c).v, scaled), its error bound e_s in distance units,
+// and whether it counts as near the cell.  e_s carries a factor 4 over the rounding
+// analysis, which also covers the few ulps of the hardware square root here; "near"
+// compares squares against a limit widened by 2^-16.  Used by the refinement's own
+// staging and by the build-time staging, which must agree bit for bit.
+struct SegStage {
+  float4 U;
+  float V;
+  float es;
+  bool nearc;
+};
+__device__ __forceinline__ SegStage stage_segment(const double4 F, const float4 G, double cx,
+                                                  double cy, double sc, float hb, float T,
+                                                  float near_lim2) {
+  SegStage r;
+  const double sC = F.z + (cx * F.x + cy * F.y);
+  const double rC = F.w + (cy * F.x - cx * F.y);
+  r.U = make_float4(G.x, G.y, (float)(sC * sc), G.z);
+  r.V = (float)(rC * sc);
+  const float fs = fabsf((float)sC), fr = fabsf((float)rC);
+  r.es = 48.0f * 0x1p-24f * (hb * 1.4143f + __builtin_amdgcn_sqrtf(fs * fs + fr * fr) + G.w);
+  const float ex = fmaxf(0.0f, fs - 0.5f * G.w);
+  r.nearc = !(ex * ex + fr * fr > near_lim2) || !(r.es <= 0.5f * T);
+  return r;
+}
+
+__device__ __forceinline__ float p2p_near_lim2(double D, float T, float hb) {
+  const float near_lim = (float)D + T + hb * 1.4143f;
+  return near_lim * near_lim * (1.0f + 0x1p-16f);
+}
+
+// Build-time staging: the records of every candidate segment of every cell, in the
+// order the refinement consumes them (candidates by id, each polyline's segments in
+// order), with the cell's E over its near segments and over all of them.  One
+// workgroup per cell.
+__global__ __launch_bounds__(256) void k_prestage(const int32_t *cand_off, const int32_t *cand_id,
+                                                  const int32_t *eoff, const double4 *frame64,
+                                                  const float4 *frame32, double x0, double y0,
+                                                  double cs, int32_t nx, int32_t ncells,
+                                                  double D, float hb, float T, float sc,
+                                                  const int64_t *rec_off, float4 *recU,
+                                                  float *recV, float2 *cellE) {
+  __shared__ float red[2][256 / GP_WAVE];
+  const float near_lim2 = p2p_near_lim2(D, T, hb);
+  for (int32_t c = blockIdx.x; c < ncells; c += gridDim.x) {
+    const double cx = x0 + ((double)(c % nx) + 0.5) * cs;
+    const double cy = y0 + ((double)(c / nx) + 0.5) * cs;
+    int64_t pos = rec_off[c];
+    float emax = 0.0f, eall = 0.0f;
+    for (int32_t k = cand_off[c]; k < cand_off[c + 1]; ++k) {
+      const int32_t f = cand_id[k];
+      const int32_t s0 = eoff[f], s1 = eoff[f + 1];
+      for (int32_t t = (int32_t)threadIdx.x; t < s1 - s0; t += blockDim.x) {
+        const SegStage r = stage_segment(frame64[s0 + t], frame32[s0 + t], cx, cy, (double)sc,
+                                         hb, T, near_lim2);
+        recU[pos + t] = r.U;
+        recV[pos + t] = r.V;
+        if (r.nearc) emax = fmaxf(emax, r.es);
+        eall = fmaxf(eall, r.es);
+      }
+      pos += s1 - s0;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      emax = fmaxf(emax, __shfl_xor(emax, off, GP_WAVE));
+      eall = fmaxf(eall, __shfl_xor(eall, off, GP_WAVE));
+    }
+    if (lane_id() == 0) {
+      red[0][threadIdx.x / GP_WAVE] = emax;
+      red[1][threadIdx.x / GP_WAVE] = eall;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < (int)(blockDim.x / GP_WAVE); ++w) {
+        emax = fmaxf(emax, red[0][w]);
+        eall = fmaxf(eall, red[1][w]);
+      }
+      cellE[c] = make_float2(emax, eall);
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_prestage(const int32_t *cand_off, const int32_t *cand_id, const int32_t *eoff,
+                           const double4 *frame64, const float4 *frame32, double x0, double y0,
+                           double cs, int32_t nx, int32_t ncells, double D, float hb, float T,
+                           float sc, const int64_t *rec_off, float4 *recU, float *recV,
+                           float2 *cellE, hipStream_t s) {
+  if (ncells <= 0) return hipSuccess;
+  const unsigned g = (unsigned)std::min<int64_t>(ncells, 65536);
+  hipLaunchKernelGGL(k_prestage, dim3(g), dim3(256), 0, s, cand_off, cand_id, eoff, frame64,
+                     frame32, x0, y0, cs, nx, ncells, D, hb, T, sc, rec_off, recU, recV, cellE);
+  return hipGetLastError();
+}
+
 template <int PPL, int W>
 __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, float *ldsV,
                             int2 *tab, int *slotseg, int *slotf, float *red, unsigned char *epi) {
@@ -1383,8 +1478,7 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
   const double cx = cell_cx(a, (uint32_t)it.cell), cy = cell_cy(a, (uint32_t)it.cell);
   const float hb = a.half_box;
   const float T = a.p2p_margin;
-  const float near_lim = (float)a.D + T + hb * 1.4143f;
-  const float near_lim2 = near_lim * near_lim * (1.0f + 0x1p-16f);
+  const float near_lim2 = p2p_near_lim2(a.D, T, hb);
   const double sc = (double)a.p2p_scale;
   const double inv_sc = 1.0 / sc;
   float px[PPL], py[PPL];
@@ -1412,21 +1506,15 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
   // Stage one segment into chunk slot t: its frame constants relative to the cell centre
   // c (s_c = -(m - c).u, r_c = -(m - c).v, scaled), and its share of the error bound E.
   auto stage = [&](int t, const double4 F, const float4 G) {
-    const double sC = F.z + (cx * F.x + cy * F.y);
-    const double rC = F.w + (cy * F.x - cx * F.y);
-    ldsU[t] = make_float4(G.x, G.y, (float)(sC * sc), G.z);
-    ldsV[t] = (float)(rC * sc);
-    // e_s and the "near the cell" test, in distance units.  The bound carries a factor 4
-    // over the rounding analysis, which also covers the few ulps of the hardware square
-    // root here; "near" compares squares against a limit widened by 2^-16.
-    const float fs = fabsf((float)sC), fr = fabsf((float)rC);
-    const float es =
-        48.0f * 0x1p-24f * (hb * 1.4143f + __builtin_amdgcn_sqrtf(fs * fs + fr * fr) + G.w);
-    const float ex = fmaxf(0.0f, fs - 0.5f * G.w);
-    const bool nearc = !(ex * ex + fr * fr > near_lim2) || !(es <= 0.5f * T);
-    if (nearc) emax = fmaxf(emax, es);
-    eall = fmaxf(eall, es);
+    const SegStage r = stage_segment(F, G, cx, cy, sc, hb, T, near_lim2);
+    ldsU[t] = r.U;
+    ldsV[t] = r.V;
+    if (r.nearc) emax = fmaxf(emax, r.es);
+    eall = fmaxf(eall, r.es);
   };
+  // With build-time staging the cell's records are read as they are, in order.
+  const bool prestaged = a.recU != nullptr && a.cseg_off == nullptr;
+  int64_t rpos = prestaged ? a.rec_off[it.cell] : 0;
   // With a segment filter the cell's chunks are slices of its list of reaching segments;
   // otherwise they are cut from its candidate polylines' whole segment ranges.
   const bool seglist = a.cseg_off != nullptr;
@@ -1482,7 +1570,8 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
       const int32_t s0 = __builtin_amdgcn_readlane(we0, q) + soff;
       const int32_t s1 = __builtin_amdgcn_readlane(we1, q);
       const int take = (s1 - s0) < (EC - filled) ? (s1 - s0) : (EC - filled);
-      for (int t = tid; t < take; t += GP_WAVE * W) slotseg[filled + t] = s0 + t;
+      if (!prestaged)
+        for (int t = tid; t < take; t += GP_WAVE * W) slotseg[filled + t] = s0 + t;
       filled += take;
       const bool cont = s0 + take < s1;
       if (tid == 0) tab[ntab] = make_int2(f, filled | (cont ? (int)0x80000000 : 0));
@@ -1491,8 +1580,15 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
       else { ++k; soff = 0; }
     }
     __syncthreads();
+    if (prestaged) {
+      for (int t = tid; t < filled; t += GP_WAVE * W) {
+        ldsU[t] = a.recU[rpos + t];
+        ldsV[t] = a.recV[rpos + t];
+      }
+      rpos += filled;
+    }
     // fill the chunk: two slots per thread per step, all four loads issued together
-    for (int t = tid; t < filled; t += 2 * GP_WAVE * W) {
+    for (int t = tid; !prestaged && t < filled; t += 2 * GP_WAVE * W) {
       const int t2 = t + GP_WAVE * W;
       const bool two = t2 < filled;
       const int sa = slotseg[t], sb = slotseg[two ? t2 : t];
@@ -1565,6 +1661,11 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
       eall = fmaxf(eall, red[4 + w]);
     }
     __syncthreads();
+  }
+  if (prestaged) {  // the cell's bounds, from the build-time staging
+    const float2 ce = a.cellE[it.cell];
+    emax = ce.x;
+    eall = ce.y;
   }
   if (!wave_live) return;
   const double E = (double)emax;

@@ -46,7 +46,8 @@ class gp_geometry(Structure):
 class gp_grid_params(Structure):
     _fields_ = [("cell_size", c_double), ("radius_D", c_double), ("x0", c_double),
                 ("y0", c_double), ("nx", c_int64), ("ny", c_int64),
-                ("pip_cell_classes", c_int32), ("p2p_segment_filter", c_int32)]
+                ("pip_cell_classes", c_int32), ("p2p_segment_filter", c_int32),
+                ("p2p_prestage", c_int32)]
 
 
 class gp_tuning(Structure):
@@ -203,8 +204,9 @@ def gp_build_grid(kind, geom, params, stream=None) -> Grid:
     """``kind`` is "pip"/"p2p" (or GP_PIP/GP_P2P); ``geom`` has numpy ``ring_vert_off``,
     ``x``, ``y`` and ``feature_ring_off`` (None for polylines); ``params`` has
     ``cell_size, radius_D, x0, y0, nx, ny`` and optionally ``cell_classes`` (PIP: 1
-    classifies every cell/polygon pair at build time) and ``segment_filter`` (P2P: 1 keeps
-    per cell only the segments within D of it, for the mixed form)."""
+    classifies every cell/polygon pair at build time), ``segment_filter`` (P2P: 1 keeps
+    per cell only the segments within D of it, for the mixed form) and ``prestage`` (P2P:
+    1 computes every cell's mixed-form segment records at build time)."""
     k = KINDS.get(kind, kind)
     g, keep = _geometry(geom)
     p = _params(params)
@@ -306,7 +308,8 @@ def _params(params):
     return gp_grid_params(float(params.cell_size), float(getattr(params, "radius_D", 0.0)),
                           float(params.x0), float(params.y0), int(params.nx), int(params.ny),
                           int(getattr(params, "cell_classes", 0)),
-                          int(getattr(params, "segment_filter", 0)))
+                          int(getattr(params, "segment_filter", 0)),
+                          int(getattr(params, "prestage", 0)))
 
 
 def gp_sweep_cell_size(kind, geom, params, cell_sizes, px, py, prec="mixed", stream=None):

@@ -398,13 +398,9 @@ def test_results_invariant_under_cell_size(gp, c1, kind):
 # ---------------------------------------------------------------- P2P segment filter
 
 
-@pytest.mark.parametrize("case", ["c2", "ties", "near", "c4"])
-def test_p2p_segment_filter_equal_unfiltered(gp, case):
-    """Per-cell segment lists (segments whose D-expanded box reaches the cell) give the
-    oracle's ids and distances bit for bit in the mixed form, perform exactly the
-    unfiltered tests minus the avoided ones, and leave the FP64 form unchanged."""
-    say("p2p segment filter", case)
-    rng = np.random.default_rng(17)
+def _p2p_case(case, rng):
+    """P2P workloads for the grid-option tests: a C2-like city, exact ties and
+    degenerate polylines, points at D +- 1e-9..1e-3 from segments, and a C4 slice."""
     if case == "c2":
         w = synth.config2(n_points=300_000, n_lines=6_000, seed_salt=7)
         g, params, px, py = w.geom, w.params, w.px, w.py
@@ -435,6 +431,17 @@ def test_p2p_segment_filter_equal_unfiltered(gp, case):
         g = synth.config4_geometry(n_lines=200_000)
         params = synth.GridParams(cell_size=100.0, radius_D=100.0, nx=400, ny=400)
         px, py = synth.config4_points(4_000_000, seed_salt=2)
+    return g, params, px, py
+
+
+@pytest.mark.parametrize("case", ["c2", "ties", "near", "c4"])
+def test_p2p_segment_filter_equal_unfiltered(gp, case):
+    """Per-cell segment lists (segments whose D-expanded box reaches the cell) give the
+    oracle's ids and distances bit for bit in the mixed form, perform exactly the
+    unfiltered tests minus the avoided ones, and leave the FP64 form unchanged."""
+    say("p2p segment filter", case)
+    rng = np.random.default_rng(17)
+    g, params, px, py = _p2p_case(case, rng)
     og = oracle.build_grid(g, params)
     if case == "c4":
         sel = rng.choice(len(px), 20_000, replace=False)
@@ -457,6 +464,43 @@ def test_p2p_segment_filter_equal_unfiltered(gp, case):
         else:
             assert st1["tests"] == st0["tests"] and st1["tests_avoided"] == 0
         say("  ", prec, "tests", st1["tests"], "avoided", st1["tests_avoided"])
+
+
+@pytest.mark.parametrize("case", ["c2", "ties", "near", "c4"])
+def test_p2p_prestage_equal_plain(gp, case):
+    """Build-time segment records give the plain grid's results bit for bit (and so the
+    oracle's) in the mixed form, under every kernel shape, with the same tests and the
+    same points sent to the FP64 recheck; the FP64 form ignores them."""
+    say("p2p prestage", case)
+    rng = np.random.default_rng(23)
+    g, params, px, py = _p2p_case(case, rng)
+    og = oracle.build_grid(g, params)
+    sel = rng.choice(len(px), min(len(px), 20_000), replace=False)
+    want_id, want_d = oracle.p2p(g, px[sel], py[sel], params.radius_D, og)
+    plain = gp.gp_build_grid("p2p", g, params)
+    pre = gp.gp_build_grid("p2p", g, synth.GridParams(**{**params.__dict__, "prestage": 1}))
+    extra = pre.info()["device_bytes"] - plain.info()["device_bytes"]
+    assert extra > 0
+    both = gp.gp_build_grid("p2p", g, synth.GridParams(**{**params.__dict__, "prestage": 1,
+                                                          "segment_filter": 1}))
+    assert both.info()["n_segment_pairs"] > 0
+    r0 = run_gpu(gp, plain, px, py, "mixed", stats=True)
+    for tn in [None, dict(points_per_lane=1, edge_chunk=64), dict(points_per_lane=2, edge_chunk=512),
+               dict(points_per_lane=4, waves_per_item=2, edge_chunk=128),
+               dict(points_per_lane=1, waves_per_item=4, edge_chunk=256, persistent=0)]:
+        gp.gp_reset_tuning(pre, "mixed")
+        r1 = run_gpu(gp, pre, px, py, "mixed", stats=True, tuning=tn)
+        assert np.array_equal(r1[0], r0[0]) and np.array_equal(r1[1], r0[1]), (case, tn)
+        check_p2p(r1[0][sel], r1[1][sel], want_id, want_d, "mixed", f"{case} prestage {tn}")
+        if tn is None:
+            assert r1[2]["tests"] == r0[2]["tests"]
+            assert r1[2]["n_rechecked"] == r0[2]["n_rechecked"]
+    gp.gp_reset_tuning(pre, "mixed")
+    r2 = run_gpu(gp, pre, px, py, "fp64")
+    r3 = run_gpu(gp, both, px, py, "mixed")
+    assert np.array_equal(r2[0], r0[0]) and np.array_equal(r2[1], r0[1])
+    assert np.array_equal(r3[0], r0[0]) and np.array_equal(r3[1], r0[1])
+    say("  extra bytes", extra, "rechecked", r0[2]["n_rechecked"])
 
 
 def test_near_edge_sweep_mixed(gp):
