@@ -236,7 +236,9 @@ gp_status gp_sweep_cell_size(gp_kind kind, const gp_geometry *geom, const gp_gri
 /* Measurement probe (not part of the join): sustained rate on the current device of
  * which = 0: FP32 FMA with every operand in a VGPR (FLOP/s), 1: FP64 FMA (FLOP/s),
  * 2: LDS broadcast 16-byte reads (wave reads/s), 3: the mixed P2P point-segment test on
- * register data (tests/s), 4: FP32 FMA with one SGPR operand (FLOP/s).  `iters` sets the
+ * register data with the segment constants in SGPRs (tests/s), 4: FP32 FMA with one
+ * SGPR operand (FLOP/s), 5: the mixed P2P test on per-lane VGPR data, four points
+ * against two segments per step (tests/s).  `iters` sets the
  * loop length; *ms receives the kernel time.  Synchronous; GP_E_INVALID_ARG for other
  * `which` or iters <= 0. */
 gp_status gp_probe_rate(int32_t which, int32_t iters, double *rate, float *ms);

@@ -1466,7 +1466,9 @@ hipError_t launch_prestage(const int32_t *cand_off, const int32_t *cand_id, cons
   return hipGetLastError();
 }
 
-template <int PPL, int W>
+// PRE: the grid carries build-time segment records (and no segment lists); the kernel
+// then holds no FP64 staging code, which keeps it within 96 VGPRs (5 waves per SIMD).
+template <int PPL, int W, bool PRE>
 __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, float *ldsV,
                             int2 *tab, int *slotseg, int *slotf, float *red, unsigned char *epi) {
   const int tid = (int)threadIdx.x;
@@ -1513,11 +1515,11 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
     eall = fmaxf(eall, r.es);
   };
   // With build-time staging the cell's records are read as they are, in order.
-  const bool prestaged = a.recU != nullptr && a.cseg_off == nullptr;
+  constexpr bool prestaged = PRE;
   int64_t rpos = prestaged ? a.rec_off[it.cell] : 0;
   // With a segment filter the cell's chunks are slices of its list of reaching segments;
   // otherwise they are cut from its candidate polylines' whole segment ranges.
-  const bool seglist = a.cseg_off != nullptr;
+  const bool seglist = !PRE && a.cseg_off != nullptr;
   int32_t k = seglist ? a.cseg_off[it.cell] : a.cand_off[it.cell];
   const int32_t k1 = seglist ? a.cseg_off[it.cell + 1] : a.cand_off[it.cell + 1];
   int32_t soff = 0;
@@ -1588,14 +1590,16 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
       rpos += filled;
     }
     // fill the chunk: two slots per thread per step, all four loads issued together
-    for (int t = tid; !prestaged && t < filled; t += 2 * GP_WAVE * W) {
-      const int t2 = t + GP_WAVE * W;
-      const bool two = t2 < filled;
-      const int sa = slotseg[t], sb = slotseg[two ? t2 : t];
-      const double4 Fa = a.frame64[sa], Fb = a.frame64[sb];
-      const float4 Ga = a.frame32[sa], Gb = a.frame32[sb];
-      stage(t, Fa, Ga);
-      if (two) stage(t2, Fb, Gb);
+    if constexpr (!PRE) {
+      for (int t = tid; t < filled; t += 2 * GP_WAVE * W) {
+        const int t2 = t + GP_WAVE * W;
+        const bool two = t2 < filled;
+        const int sa = slotseg[t], sb = slotseg[two ? t2 : t];
+        const double4 Fa = a.frame64[sa], Fb = a.frame64[sb];
+        const float4 Ga = a.frame32[sa], Gb = a.frame32[sb];
+        stage(t, Fa, Ga);
+        if (two) stage(t2, Fb, Gb);
+      }
     }
     __syncthreads();
     if (!wave_live) continue;
@@ -1645,27 +1649,30 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
       start = end;
     }
   }
-  // E = maximum over the whole workgroup's staged segments
-  for (int off = 32; off > 0; off >>= 1) {
-    emax = fmaxf(emax, __shfl_xor(emax, off, GP_WAVE));
-    eall = fmaxf(eall, __shfl_xor(eall, off, GP_WAVE));
-  }
-  if (W > 1) {
-    if (lane == 0) {
-      red[wave] = emax;
-      red[4 + wave] = eall;
-    }
-    __syncthreads();
-    for (int w = 0; w < W; ++w) {
-      emax = fmaxf(emax, red[w]);
-      eall = fmaxf(eall, red[4 + w]);
-    }
-    __syncthreads();
-  }
-  if (prestaged) {  // the cell's bounds, from the build-time staging
+  if constexpr (PRE) {  // the cell's bounds, from the build-time staging
     const float2 ce = a.cellE[it.cell];
     emax = ce.x;
     eall = ce.y;
+    // the exact pass reuses the chunk's LDS: every wave of the item must be done with it
+    if (W > 1) __syncthreads();
+  } else {
+    // E = maximum over the whole workgroup's staged segments
+    for (int off = 32; off > 0; off >>= 1) {
+      emax = fmaxf(emax, __shfl_xor(emax, off, GP_WAVE));
+      eall = fmaxf(eall, __shfl_xor(eall, off, GP_WAVE));
+    }
+    if (W > 1) {
+      if (lane == 0) {
+        red[wave] = emax;
+        red[4 + wave] = eall;
+      }
+      __syncthreads();
+      for (int w = 0; w < W; ++w) {
+        emax = fmaxf(emax, red[w]);
+        eall = fmaxf(eall, red[4 + w]);
+      }
+      __syncthreads();
+    }
   }
   if (!wave_live) return;
   const double E = (double)emax;
@@ -1850,8 +1857,8 @@ __global__ __launch_bounds__(64 * W) void k_p2p64(RefineArgs a, int persistent) 
   }
 }
 
-template <int PPL, int W>
-__global__ __launch_bounds__(64 * W) void k_p2pmix(RefineArgs a, int persistent) {
+template <int PPL, int W, bool PRE>
+__device__ __forceinline__ void p2pmix_loop(const RefineArgs &a, int persistent) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t s_item;
   __shared__ float red[8];
@@ -1863,10 +1870,21 @@ __global__ __launch_bounds__(64 * W) void k_p2pmix(RefineArgs a, int persistent)
   const uint32_t n_items = *a.n_items;
   uint32_t it = persistent ? (W == 1 ? next_item(a) : next_item_wg(a, &s_item)) : blockIdx.x;
   while (it < n_items) {
-    p2pmix_item<PPL, W>(a, a.items[it], U, V, tab, slotseg, slotf, red, smem);
+    p2pmix_item<PPL, W, PRE>(a, a.items[it], U, V, tab, slotseg, slotf, red, smem);
     if (!persistent) break;
     it = W == 1 ? next_item(a) : next_item_wg(a, &s_item);
   }
+}
+
+template <int PPL, int W>
+__global__ __launch_bounds__(64 * W) void k_p2pmix(RefineArgs a, int persistent) {
+  p2pmix_loop<PPL, W, false>(a, persistent);
+}
+
+// The same refinement on a grid with build-time segment records.
+template <int PPL, int W>
+__global__ __launch_bounds__(64 * W) void k_p2pmix_pre(RefineArgs a, int persistent) {
+  p2pmix_loop<PPL, W, true>(a, persistent);
 }
 
 static size_t refine_lds_bytes(gp_kind kind, gp_precision prec, int ec, int W) {
@@ -1925,6 +1943,8 @@ hipError_t launch_refine(gp_kind kind, gp_precision prec, const RefineArgs &a,
     GP_DISPATCH(k_pipmix, ppl, dim3(grid), blk, lds, s, a, pers);
   else if (prec == GP_FP64)
     GP_DISPATCH_W(k_p2p64, ppl, W, dim3(grid), blk, lds, s, a, pers);
+  else if (a.recU)
+    GP_DISPATCH_W(k_p2pmix_pre, ppl, W, dim3(grid), blk, lds, s, a, pers);
   else
     GP_DISPATCH_W(k_p2pmix, ppl, W, dim3(grid), blk, lds, s, a, pers);
   return hipGetLastError();

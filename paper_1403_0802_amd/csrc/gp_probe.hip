@@ -97,14 +97,47 @@ __global__ __launch_bounds__(256) void k_p2p_mix_regs(uint32_t *out, int iters, 
   out[blockIdx.x * blockDim.x + threadIdx.x] = m0 ^ m1;
 }
 
+// The same test in the refinement loop's shape: four points per lane against two
+// segments per step, every operand in a VGPR (the segment constants differ per lane,
+// as after an LDS read), the running minimum with v_min3.
+__global__ __launch_bounds__(256) void k_p2p_mix_vregs(uint32_t *out, int iters, float4 U0,
+                                                       float4 U1, float R0, float R1) {
+  const float o = (float)(threadIdx.x & 63) * 1e-6f;
+  U0.x += o; U0.y -= o; U0.z += o; U0.w += o;
+  U1.x -= o; U1.y += o; U1.z -= o; U1.w += o;
+  R0 += o;
+  R1 -= o;
+  float px[4], py[4];
+  uint32_t m[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    px[j] = threadIdx.x * 1e-3f + 0.25f * j;
+    py[j] = blockIdx.x * 1e-3f - 0.125f * j;
+    m[j] = 0x7f800000u;
+  }
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      m[j] = min(m[j], min(probe_seg(px[j], py[j], U0, R0), probe_seg(px[j], py[j], U1, R1)));
+    // perturb the constants so nothing is loop-invariant (4 extra adds per 8 tests, in
+    // place of the loop's address moves)
+    U0.z += 1e-6f;
+    U1.z -= 1e-6f;
+    R0 += 1e-6f;
+    R1 -= 1e-6f;
+  }
+  out[blockIdx.x * blockDim.x + threadIdx.x] = m[0] ^ m[1] ^ m[2] ^ m[3];
+}
+
 }  // namespace
 
 // which: 0 FP32 FMA on VGPR operands, 1 FP64 FMA, 2 LDS broadcast 16-byte reads, 3 the
-// P2P test on register data, 4 FP32 FMA with an SGPR operand.  Returns the achieved
-// rate: FLOP/s (0, 1, 4), wave-level broadcast reads per second (2) or tests per second
-// (3).
+// P2P test on register data with the segment constants in SGPRs, 4 FP32 FMA with an
+// SGPR operand, 5 the P2P test on per-lane VGPR data in the refinement loop's shape.
+// Returns the achieved rate: FLOP/s (0, 1, 4), wave-level broadcast reads per second (2)
+// or tests per second (3, 5).
 extern "C" gp_status gp_probe_rate(int32_t which, int32_t iters, double *rate, float *ms) {
-  if (!rate || iters <= 0 || which < 0 || which > 4)
+  if (!rate || iters <= 0 || which < 0 || which > 5)
     return set_error(GP_E_INVALID_ARG, "bad probe arguments");
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -140,6 +173,12 @@ extern "C" gp_status gp_probe_rate(int32_t which, int32_t iters, double *rate, f
       case 2:
         hipLaunchKernelGGL(k_lds_bcast, dim3(blocks), dim3(threads), 0, nullptr, (float *)buf, iters);
         work = nthr / 64.0 * iters * 4;  // wave-level broadcast reads
+        break;
+      case 5:
+        hipLaunchKernelGGL(k_p2p_mix_vregs, dim3(blocks), dim3(threads), 0, nullptr,
+                           (uint32_t *)buf, iters, make_float4(0.1f, 0.2f, 0.3f, 0.4f),
+                           make_float4(0.5f, 0.6f, 0.7f, 0.8f), 0.9f, 1.1f);
+        work = nthr * iters * 8;
         break;
       default:
         hipLaunchKernelGGL(k_p2p_mix_regs, dim3(blocks), dim3(threads), 0, nullptr,
