@@ -80,10 +80,10 @@ def write_traffic(fetch_csv: str, write_csv: str):
         per[counter] = {"copy_factor": factor}
         for r in rows:
             name = r["Kernel_Name"]
-            for k in ("k_p2pmix", "k_pipmix", "k_p2p64", "k_pip64"):
+            for k in ("k_p2pmix_pre", "k_p2pmix", "k_pipmix", "k_p2p64", "k_pip64"):
                 if f"gp::{k}<" in name:
                     per[counter].setdefault(k, []).append(float(r["Counter_Value"]))
-    for k in ("k_p2pmix", "k_pipmix", "k_p2p64", "k_pip64"):
+    for k in ("k_p2pmix_pre", "k_p2pmix", "k_pipmix", "k_p2p64", "k_pip64"):
         f = per["FETCH_SIZE"].get(k)
         w = per["WRITE_SIZE"].get(k)
         ff, wf = per["FETCH_SIZE"]["copy_factor"], per["WRITE_SIZE"]["copy_factor"]
@@ -109,11 +109,14 @@ def build_workloads(scale: float):
     from paper_1403_0802_amd import synth
     t0 = time.time()
     geom3, info3 = synth.config3_geometry()
-    p3 = synth.GridParams(cell_size=1 / 1024, nx=1024, ny=1024)
+    # 1/512: the fastest PIP query of the cell-size sweep (bench.py --cell-sweep)
+    p3 = synth.GridParams(cell_size=1 / 512, nx=512, ny=512)
     n3 = int(50_000_000 * scale)
     px3, py3 = synth.config3_points(n3)
     geom4 = synth.config4_geometry()
-    p4 = synth.GridParams(cell_size=100.0, radius_D=100.0, nx=400, ny=400)
+    # the P2P grid carries its build-time segment records (p2p_prestage), an index
+    # structure like the candidate lists; detail.p2p_plain_grid runs the grid without them
+    p4 = synth.GridParams(cell_size=100.0, radius_D=100.0, nx=400, ny=400, prestage=1)
     n4 = int(200_000_000 * scale)
     px4, py4 = synth.config4_points(n4)
     log(f"[bench] inputs generated in {time.time() - t0:.1f}s: C3 {n3} pts / "
@@ -382,7 +385,8 @@ def main():
     pip_flops = tests_pip * F_PIP / (pip_ref / 1e3)
     p2p_flops = tests_p2p * F_P2P / (p2p_ref / 1e3)
     dom = "p2p" if p2p_ref >= pip_ref else "pip"
-    dom_kernel = "k_p2pmix" if dom == "p2p" else "k_pipmix"
+    p2p_kernel = "k_p2pmix_pre" if getattr(p4, "prestage", 0) else "k_p2pmix"
+    dom_kernel = p2p_kernel if dom == "p2p" else "k_pipmix"
     achieved = p2p_flops if dom == "p2p" else pip_flops
     workload = WORKLOAD_NAME
     if args.scale != 1.0:
@@ -407,10 +411,12 @@ def main():
     # the mixed P2P test's instruction mix on register data.
     probes = {}
     for key, which, iters in (("fp32_fma_vgpr_tflops", 0, 20000), ("fp32_fma_sgpr_tflops", 4, 20000),
-                              ("fp64_fma_tflops", 1, 10000), ("p2p_test_regs_tests_per_s", 3, 5000)):
+                              ("fp64_fma_tflops", 1, 10000),
+                              ("p2p_test_sgpr_consts_tests_per_s", 3, 5000),
+                              ("p2p_test_vgpr_tests_per_s", 5, 20000)):
         r, _ = gp.gp_probe_rate(which, iters)
         probes[key] = r / 1e12 if key.endswith("tflops") else r
-    probes["p2p_refine_vs_regs_probe"] = (tests_p2p / (p2p_ref / 1e3)) / probes["p2p_test_regs_tests_per_s"]
+    probes["p2p_refine_vs_vgpr_probe"] = (tests_p2p / (p2p_ref / 1e3)) / probes["p2p_test_vgpr_tests_per_s"]
     detail["probes"] = probes
     # PIP with cell classes (Sec. III.A): points in cells wholly inside a polygon take its
     # id untested, cells outside are skipped; same ids, fewer tests (reported apart from
@@ -460,12 +466,11 @@ def main():
             "segment_pairs": info["n_segment_pairs"], "grid_bytes": info["device_bytes"],
             "grid_build_ms": build_f}
         del grid4f, id4f, d4f
-    # P2P with build-time segment records: every cell's mixed-form records (20 bytes per
-    # cell/segment pair) are computed once with the resident grid; same tests, same
-    # results (reported apart from the headline)
+    # P2P on the grid without build-time segment records: the kernel stages every
+    # segment's cell-relative record itself; same tests, same results
     if not args.no_classes:
         from paper_1403_0802_amd import synth
-        p4p = synth.GridParams(**{**p4.__dict__, "prestage": 1})
+        p4p = synth.GridParams(**{**p4.__dict__, "prestage": 0})
         t0 = time.perf_counter()
         grid4p = gp.gp_build_grid("p2p", geom4, p4p)
         build_p = 1e3 * (time.perf_counter() - t0)
@@ -475,12 +480,13 @@ def main():
         d4p = torch.empty_like(d4)
         gp.gp_p2p(grid4p, x4, y4, id4p, d4p, prec, ws4, stream, False)
         stp = [gp.gp_p2p(grid4p, x4, y4, id4p, d4p, prec, ws4, stream, True) for _ in range(3)]
-        detail["p2p_prestage"] = {
+        detail["p2p_plain_grid"] = {
             "ms": avg(stp, "ms_total"), "ms_refine": avg(stp, "ms_refine"),
-            "ms_refine_without": avg(st_p2p, "ms_refine"), "tests": stp[0]["tests"],
+            "ms_refine_with_records": avg(st_p2p, "ms_refine"), "tests": stp[0]["tests"],
             "refine_tests_per_s": stp[0]["tests"] / (avg(stp, "ms_refine") / 1e3),
-            "same_as_plain": bool(torch.equal(id4p, id4) and torch.equal(d4p, d4)),
-            "grid_bytes": grid4p.info()["device_bytes"], "grid_build_ms": build_p}
+            "same_as_headline": bool(torch.equal(id4p, id4) and torch.equal(d4p, d4)),
+            "grid_bytes": grid4p.info()["device_bytes"],
+            "grid_bytes_with_records": grid4.info()["device_bytes"], "grid_build_ms": build_p}
         del grid4p, id4p, d4p
     # the FP64 form on the same inputs, for comparison
     if not args.no_fp64:
