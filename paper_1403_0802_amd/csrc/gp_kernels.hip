@@ -1509,8 +1509,8 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
   // c (s_c = -(m - c).u, r_c = -(m - c).v, scaled), and its share of the error bound E.
   auto stage = [&](int t, const double4 F, const float4 G) {
     const SegStage r = stage_segment(F, G, cx, cy, sc, hb, T, near_lim2);
-    ldsU[t] = r.U;
-    ldsV[t] = r.V;
+    ldsU[2 * t] = r.U;
+    ldsV[8 * t] = r.V;
     if (r.nearc) emax = fmaxf(emax, r.es);
     eall = fmaxf(eall, r.es);
   };
@@ -1584,8 +1584,8 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
     __syncthreads();
     if (prestaged) {
       for (int t = tid; t < filled; t += GP_WAVE * W) {
-        ldsU[t] = a.recU[rpos + t];
-        ldsV[t] = a.recV[rpos + t];
+        ldsU[2 * t] = a.recU[rpos + t];
+        ldsV[8 * t] = a.recV[rpos + t];
       }
       rpos += filled;
     }
@@ -1610,18 +1610,17 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
       const int end = te.y & 0x7fffffff;
       int t = start;
       for (; t + 2 <= end; t += 2) {
-        // t can be odd (a polyline starts anywhere in the chunk): two 4-byte reads, not
-        // one misaligned 8-byte read, which the LDS serves at a fraction of the rate
-        const float4 u0 = ldsU[t], u1 = ldsU[t + 1];
-        const float v0 = ldsV[t], v1 = ldsV[t + 1];
+        // two slots per step: four LDS reads off one address (32-byte slots)
+        const float4 u0 = ldsU[2 * t], u1 = ldsU[2 * t + 2];
+        const float v0 = ldsV[8 * t], v1 = ldsV[8 * t + 8];
 #pragma unroll
         for (int j = 0; j < PPL; ++j)
           pm[j] = min(pm[j], min(seg_d2_bits(px[j], py[j], u0, v0),
                                  seg_d2_bits(px[j], py[j], u1, v1)));
       }
       if (t < end) {
-        const float4 u0 = ldsU[t];
-        const float v0 = ldsV[t];
+        const float4 u0 = ldsU[2 * t];
+        const float v0 = ldsV[8 * t];
 #pragma unroll
         for (int j = 0; j < PPL; ++j) pm[j] = min(pm[j], seg_d2_bits(px[j], py[j], u0, v0));
       }
@@ -1862,9 +1861,11 @@ __device__ __forceinline__ void p2pmix_loop(const RefineArgs &a, int persistent)
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t s_item;
   __shared__ float red[8];
+  // slot t of the chunk is 32 bytes at U + 2t: the record's float4 U, then its V, so one
+  // address register serves both reads of a slot and of its neighbour
   float4 *U = (float4 *)smem;
-  float *V = (float *)(U + a.edge_chunk);
-  int2 *tab = (int2 *)(V + a.edge_chunk);
+  float *V = (float *)(U + 1);
+  int2 *tab = (int2 *)(U + 2 * a.edge_chunk);
   int *slotseg = (int *)(tab + a.edge_chunk);
   int *slotf = slotseg + a.edge_chunk;
   const uint32_t n_items = *a.n_items;
@@ -1892,7 +1893,7 @@ static size_t refine_lds_bytes(gp_kind kind, gp_precision prec, int ec, int W) {
     return prec == GP_FP64 ? (size_t)ec * sizeof(PipRec64) : (size_t)ec * (16 + 16 + 4);
   if (prec == GP_FP64) return (size_t)ec * (sizeof(SegRec64) + sizeof(int2));
   // the chunk (segment records, polyline table, slot map), reused by the exact pass
-  const size_t chunk = (size_t)ec * (16 + 4 + sizeof(int2) + 2 * sizeof(int));
+  const size_t chunk = (size_t)ec * (32 + sizeof(int2) + 2 * sizeof(int));
   const size_t epi = (size_t)W * P2P_EPI_BYTES;
   return chunk > epi ? chunk : epi;
 }
