@@ -342,6 +342,16 @@ extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
     if (npairs)
       GP_TRY_HIP_G(hipMemcpyAsync(g->d_cand_id, svals, (size_t)npairs * 4,
                                   hipMemcpyDeviceToDevice, s));
+    if (kind == GP_P2P) {
+      // near-segment range of each (cell, candidate) pair, for the mixed form's exact pass
+      DevBuf rc;
+      GP_TRY_HIP_G(rc.alloc((size_t)std::max<int64_t>(nedges, 1) * 16));
+      GP_TRY_HIP_G(hipMalloc(&g->d_near, np * 8));
+      GP_TRY_HIP_G(launch_near_ranges(g->d_edge64, (int32_t)nedges, D, cs * 0x1p-20, x0, y0, cs,
+                                      g->nx, g->ny, skeys, g->d_cand_id, (int32_t)npairs,
+                                      g->d_eoff, (int4 *)rc.p, g->d_near, s));
+      GP_TRY_HIP_G(hipStreamSynchronize(s));
+    }
     if (kind == GP_PIP && params->pip_cell_classes) {
       // margin of the cell classes: the MBB pad, or more where coordinates are large
       const double M = std::max({std::fabs(x0), std::fabs(y0), std::fabs(x0 + (double)nx * cs),
@@ -455,6 +465,7 @@ extern "C" void gp_grid_free(gp_grid *g) {
   (void)hipFree(g->d_cseg);
   (void)hipFree(g->d_seg2f);
   (void)hipFree(g->d_cell_segs);
+  (void)hipFree(g->d_near);
   (void)hipFree(g->d_rec_off);
   (void)hipFree(g->d_recU);
   (void)hipFree(g->d_recV);
@@ -467,7 +478,7 @@ static int64_t grid_device_bytes(const Grid &g) {
   const int64_t ne = std::max<int64_t>(g.nedges, 1), nc = std::max<int64_t>(g.ncells, 1);
   const int64_t np = std::max<int64_t>(g.npairs, 1);
   int64_t b = ((int64_t)g.nf + 1) * 4 + ne * (32 + 4) + (nc + 1) * 4 + np * 4 + nc * 8;
-  if (g.kind == GP_P2P) b += ne * (32 + 16) + (ne + P2P_BLOCK - 1) / P2P_BLOCK * 32;
+  if (g.kind == GP_P2P) b += ne * (32 + 16) + (ne + P2P_BLOCK - 1) / P2P_BLOCK * 32 + np * 8;
   if (g.d_cand_class) b += np + nc * 8;
   if (g.d_cseg_off) b += (nc + 1) * 4 + std::max<int64_t>(g.ncseg, 1) * 4 + ne * 4 + nc * 8;
   if (g.d_recU) b += (nc + 1) * 8 + std::max<int64_t>(g.nrec, 1) * 20 + nc * 8;
@@ -620,6 +631,7 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   a.frame64 = g->d_frame64;
   a.frame32 = g->d_frame32;
   a.circ = g->d_circ;
+  a.near = g->d_near;
   a.cand_class = g->d_cand_class;
   const bool segf = prec == GP_MIXED && g->d_cseg_off != nullptr;
   a.cseg_off = segf ? g->d_cseg_off : nullptr;

@@ -46,6 +46,7 @@ struct RefineArgs {
   const float *recV;         //   records in refinement order, from rec_off[cell]
   const int64_t *rec_off;    //   [ncells+1]
   const float2 *cellE;       //   [ncells] E over near segments, E over all
+  const int2 *near;          // P2P: [npairs] near-segment range of each (cell, candidate)
   double x0, y0, cs;
   int32_t nx, ncells;
   double D, D2, D2_next;     // P2P: D, fl(D*D), the smallest double above fl(D*D)
@@ -90,6 +91,7 @@ struct Grid {
   int32_t *d_seg2f;       // [nedges]
   int64_t *d_cell_segs;   // [ncells] segments per cell
   int64_t ncseg;
+  int2 *d_near;           // P2P: near-segment range per (cell, candidate) pair
   float4 *d_recU;         // P2P build-time staging (p2p_prestage)
   float *d_recV;
   int64_t *d_rec_off;
@@ -156,6 +158,10 @@ hipError_t launch_histogram(const uint32_t *keys, size_t n, uint32_t *cnt, hipSt
 hipError_t launch_cell_edges(const int32_t *cand_off, const int32_t *cand_id,
                              const int32_t *eoff, const uint8_t *cand_class, int32_t ncells,
                              int64_t *cell_edges, hipStream_t s);
+hipError_t launch_near_ranges(const double4 *seg64, int32_t nseg, double D, double pad,
+                              double x0, double y0, double cs, int32_t nx, int32_t ny,
+                              const uint32_t *pair_cell, const int32_t *cand_id, int32_t npairs,
+                              const int32_t *eoff, int4 *rc, int2 *near, hipStream_t s);
 hipError_t launch_prestage(const int32_t *cand_off, const int32_t *cand_id, const int32_t *eoff,
                            const double4 *frame64, const float4 *frame32, double x0, double y0,
                            double cs, int32_t nx, int32_t ncells, double D, float hb, float T,

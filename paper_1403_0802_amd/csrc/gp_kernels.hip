@@ -460,15 +460,21 @@ hipError_t launch_build_circles(const double4 *seg64, int32_t nseg, double4 *cir
   return hipGetLastError();
 }
 
-// Bounding box of each segment, expanded by D and padded like the feature MBBs, in the
-// MBB layout the rasteriser takes.
+// Bounding box of a segment, expanded by D and padded like the feature MBBs:
+// (min x, min y, max x, max y).
+__device__ __forceinline__ double4 seg_box(const double4 r, double D, double pad) {
+  return make_double4((fmin(r.x, r.z) - D) - pad, (fmin(r.y, r.w) - D) - pad,
+                      (fmax(r.x, r.z) + D) + pad, (fmax(r.y, r.w) + D) + pad);
+}
+
+// Each segment's box, in the MBB layout the rasteriser takes.
 __global__ void k_seg_boxes(const double4 *seg, int32_t nseg, double D, double pad, double *box) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += gridDim.x * blockDim.x) {
-    const double4 r = seg[i];
-    box[4 * (size_t)i + 0] = (fmin(r.x, r.z) - D) - pad;
-    box[4 * (size_t)i + 1] = (fmin(r.y, r.w) - D) - pad;
-    box[4 * (size_t)i + 2] = (fmax(r.x, r.z) + D) + pad;
-    box[4 * (size_t)i + 3] = (fmax(r.y, r.w) + D) + pad;
+    const double4 b = seg_box(seg[i], D, pad);
+    box[4 * (size_t)i + 0] = b.x;
+    box[4 * (size_t)i + 1] = b.y;
+    box[4 * (size_t)i + 2] = b.z;
+    box[4 * (size_t)i + 3] = b.w;
   }
 }
 
@@ -597,6 +603,72 @@ hipError_t launch_raster_count(const double *mbb, int32_t nf, double x0, double 
                                int32_t nx, int32_t ny, uint32_t *cnt, hipStream_t s) {
   hipLaunchKernelGGL(k_raster_count, dim3(grid_for(nf + 1, 256, 8192)), dim3(256), 0, s, mbb,
                      nf, x0, y0, cs, nx, ny, cnt);
+  return hipGetLastError();
+}
+
+// The cells every segment's box reaches (the rasteriser's ranges of seg_box, so exactly
+// the cells a segment list would hold it in): (x lo, x hi, y lo, y hi), empty when the
+// box misses the grid.
+__global__ void k_seg_cells(const double4 *seg, int32_t nseg, double D, double pad, double x0,
+                            double y0, double cs, int32_t nx, int32_t ny, int4 *rc) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += gridDim.x * blockDim.x) {
+    const double4 b = seg_box(seg[i], D, pad);
+    int32_t ax, bx, ay, by;
+    if (axis_range(b.x, b.z, x0, cs, nx, &ax, &bx) && axis_range(b.y, b.w, y0, cs, ny, &ay, &by))
+      rc[i] = make_int4(ax, bx, ay, by);
+    else
+      rc[i] = make_int4(1, 0, 1, 0);
+  }
+}
+
+// Near-segment range of every (cell, candidate polyline) pair: from the first to one past
+// the last of the polyline's segments whose box reaches the cell; the polyline's first
+// segment alone when none does (then every segment is farther than D from the whole
+// cell).  A segment within D of a point of the cell is inside the range, so the exact
+// pass's minimum over the range equals the polyline's whenever that minimum is in range.
+// One wave per pair, lanes over segments.
+__global__ __launch_bounds__(256) void k_near_ranges(const uint32_t *pair_cell,
+                                                     const int32_t *cand_id, int32_t npairs,
+                                                     const int32_t *eoff, const int4 *rc,
+                                                     int32_t nx, int2 *near) {
+  const uint32_t lane = lane_id();
+  const int32_t nw = (int32_t)(gridDim.x * (blockDim.x / GP_WAVE));
+  for (int32_t k = (int32_t)(blockIdx.x * (blockDim.x / GP_WAVE) + threadIdx.x / GP_WAVE);
+       k < npairs; k += nw) {
+    const int32_t cell = (int32_t)pair_cell[k];
+    const int32_t cx = cell % nx, cy = cell / nx;
+    const int32_t f = cand_id[k];
+    const int32_t s0 = eoff[f], s1 = eoff[f + 1];
+    int32_t lo = -1, hi = -1;
+    for (int32_t base = s0; base < s1; base += GP_WAVE) {
+      const int32_t sg = base + (int32_t)lane;
+      bool nr = false;
+      if (sg < s1) {
+        const int4 r = rc[sg];
+        nr = cx >= r.x && cx <= r.y && cy >= r.z && cy <= r.w;
+      }
+      const uint64_t m = ballot(nr);
+      if (m) {
+        if (lo < 0) lo = base + (int32_t)__builtin_ctzll(m);
+        hi = base + 63 - (int32_t)__builtin_clzll(m);
+      }
+    }
+    if (lane == 0) near[k] = lo < 0 ? make_int2(s0, s0 + 1) : make_int2(lo, hi + 1);
+  }
+}
+
+hipError_t launch_near_ranges(const double4 *seg64, int32_t nseg, double D, double pad,
+                              double x0, double y0, double cs, int32_t nx, int32_t ny,
+                              const uint32_t *pair_cell, const int32_t *cand_id, int32_t npairs,
+                              const int32_t *eoff, int4 *rc, int2 *near, hipStream_t s) {
+  if (nseg <= 0 || npairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seg_cells, dim3(grid_for(nseg, 256, 8192)), dim3(256), 0, s, seg64, nseg,
+                     D, pad, x0, y0, cs, nx, ny, rc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t blocks = std::min<int64_t>(((int64_t)npairs + 3) / 4, 65536);
+  hipLaunchKernelGGL(k_near_ranges, dim3((unsigned)blocks), dim3(256), 0, s, pair_cell, cand_id,
+                     npairs, eoff, rc, nx, near);
   return hipGetLastError();
 }
 
@@ -1568,7 +1640,6 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
         we1 = a.eoff[wf + 1];
       }
       const int q = k - kw;
-      const int32_t f = __builtin_amdgcn_readlane(wf, q);
       const int32_t s0 = __builtin_amdgcn_readlane(we0, q) + soff;
       const int32_t s1 = __builtin_amdgcn_readlane(we1, q);
       const int take = (s1 - s0) < (EC - filled) ? (s1 - s0) : (EC - filled);
@@ -1576,7 +1647,8 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
         for (int t = tid; t < take; t += GP_WAVE * W) slotseg[filled + t] = s0 + t;
       filled += take;
       const bool cont = s0 + take < s1;
-      if (tid == 0) tab[ntab] = make_int2(f, filled | (cont ? (int)0x80000000 : 0));
+      // the table names the candidate by its index k (ids ascend with k within a cell)
+      if (tid == 0) tab[ntab] = make_int2(k, filled | (cont ? (int)0x80000000 : 0));
       ++ntab;
       if (cont) soff += take;
       else { ++k; soff = 0; }
@@ -1686,6 +1758,8 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
   // LDS atomic minimum.  Non-negative doubles order like their bit patterns, so the
   // result is the exact minimum over the polyline's segments whatever the order.
   const double Ep = (double)eall;
+  // f1/f2 hold candidate indices, or polyline ids when the chunks come from segment lists
+  const bool byk = !seglist;
   wave_lds_sync();  // with one wave per item the chunk's LDS is reused without a barrier
   unsigned char *wepi = epi + wave * P2P_EPI_BYTES;
   uint64_t *res = (uint64_t *)wepi;                  // [2*64] result bits per pair
@@ -1726,8 +1800,15 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
     const int ncand = miss ? 0 : (d2 - d1 > 2.0 * E) ? 1 : (d3 - d1 > 2.0 * E) ? 2 : 3;
     const int nc = (v && (ncand == 1 || ncand == 2)) ? ncand : 0;
     int32_t s00 = 0, s01 = 0, s10 = 0, s11 = 0;
-    if (nc >= 1) { s00 = a.eoff[f1[j]]; s01 = a.eoff[f1[j] + 1]; }
-    if (nc >= 2) { s10 = a.eoff[f2[j]]; s11 = a.eoff[f2[j] + 1]; }
+    // with candidate indices (no segment lists) only the candidate's near-segment range
+    // of this cell can hold a minimum within D; with segment lists, the whole polyline
+    if (byk) {
+      if (nc >= 1) { const int2 r = a.near[f1[j]]; s00 = r.x; s01 = r.y; }
+      if (nc >= 2) { const int2 r = a.near[f2[j]]; s10 = r.x; s11 = r.y; }
+    } else {
+      if (nc >= 1) { s00 = a.eoff[f1[j]]; s01 = a.eoff[f1[j] + 1]; }
+      if (nc >= 2) { s10 = a.eoff[f2[j]]; s11 = a.eoff[f2[j] + 1]; }
+    }
     // blocks overlapped by a pair's segments (every polyline has at least one segment)
     const int u0 = nc >= 1 ? (s01 - 1) / P2P_BLOCK - s00 / P2P_BLOCK + 1 : 0;
     const int u1 = nc >= 2 ? (s11 - 1) / P2P_BLOCK - s10 / P2P_BLOCK + 1 : 0;
@@ -1786,7 +1867,8 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
       int32_t bid = -1;
       double best = INFINITY;
       for (int c = 0; c < nc; ++c) {
-        const int32_t f = c == 0 ? f1[j] : f2[j];
+        const int32_t fk = c == 0 ? f1[j] : f2[j];
+        const int32_t f = byk ? a.cand_id[fk] : fk;
         const double pd = __longlong_as_double((long long)res[pid + c]);
         if (pd <= a.D2 && (pd < best || (pd == best && f < bid))) { best = pd; bid = f; }
       }
