@@ -1760,6 +1760,14 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
   const double Ep = (double)eall;
   // f1/f2 hold candidate indices, or polyline ids when the chunks come from segment lists
   const bool byk = !seglist;
+  // results are stored after all point slots: on this GPU a store holds back every later
+  // load's wait (one counter covers both), so stores between slots would stall the
+  // next slot's loads on their scattered writes
+  int32_t rid[PPL];
+  double rdd[PPL];
+  bool rw[PPL];
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) { rid[j] = -1; rdd[j] = INFINITY; rw[j] = false; }
   wave_lds_sync();  // with one wave per item the chunk's LDS is reused without a barrier
   unsigned char *wepi = epi + wave * P2P_EPI_BYTES;
   uint64_t *res = (uint64_t *)wepi;                  // [2*64] result bits per pair
@@ -1872,16 +1880,24 @@ __device__ void p2pmix_item(const RefineArgs &a, const Item it, float4 *ldsU, fl
         const double pd = __longlong_as_double((long long)res[pid + c]);
         if (pd <= a.D2 && (pd < best || (pd == best && f < bid))) { best = pd; bid = f; }
       }
-      const uint32_t o = a.perm[it.pt_lo + idx];
-      a.out_id[o] = bid;
-      a.out_dist[o] = bid >= 0 ? sqrt(best) : INFINITY;
+      rid[j] = bid;
+      rdd[j] = bid >= 0 ? sqrt(best) : INFINITY;
+      rw[j] = true;
     } else if (v && miss) {
-      const uint32_t o = a.perm[it.pt_lo + idx];
-      a.out_id[o] = -1;
-      a.out_dist[o] = INFINITY;
+      rid[j] = -1;
+      rdd[j] = INFINITY;
+      rw[j] = true;
     }
     push_recheck(a, v && ncand == 3, (uint32_t)(it.pt_lo + idx));
     wave_lds_sync();  // the next point slot reuses the pass's LDS
+  }
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    if (rw[j]) {
+      const uint32_t o = a.perm[wbase + (int)lane + GP_WAVE * j + it.pt_lo];
+      a.out_id[o] = rid[j];
+      a.out_dist[o] = rdd[j];
+    }
   }
 }
 
