@@ -60,10 +60,12 @@ struct DevBuf {
 };
 }  // namespace
 
-// Defaults from autotuning on the configuration-3/4 workloads (gp_autotune re-tunes).
+// Defaults from full-size sweeps on the configuration-3/4 workloads (gp_autotune
+// re-tunes): mixed P2P 4 points per lane, mixed PIP 2 (its per-item edge staging is
+// shared by 128 points), FP64 forms 1.
 static gp_tuning default_tuning(gp_kind kind, gp_precision prec) {
   gp_tuning t;
-  t.points_per_lane = (prec == GP_MIXED && kind == GP_P2P) ? 4 : 1;
+  t.points_per_lane = prec == GP_MIXED ? (kind == GP_P2P ? 4 : 2) : 1;
   t.edge_chunk = prec == GP_MIXED ? 128 : 256;
   t.wg_per_cu = (prec == GP_MIXED && kind == GP_P2P) ? 32 : 16;
   t.persistent = (prec == GP_MIXED && kind == GP_PIP) ? 0 : 1;
