@@ -655,9 +655,10 @@ def test_grid_and_option_limits(gp):
         with pytest.raises(gp.GPError) as e:
             gp.gp_build_grid("pip", g, params)
         assert e.value.status == gp.GP_E_CAPACITY, params
-    with pytest.raises(gp.GPError) as e:
-        gp.gp_build_grid("pip", g, synth.GridParams(cell_size=0.5, cell_classes=2))
-    assert e.value.status == gp.GP_E_INVALID_ARG
+    for bad in (dict(cell_classes=2), dict(segment_filter=-1), dict(prestage=2)):
+        with pytest.raises(gp.GPError) as e:
+            gp.gp_build_grid("pip", g, synth.GridParams(cell_size=0.5, **bad))
+        assert e.value.status == gp.GP_E_INVALID_ARG, bad
     grid = gp.gp_build_grid("pip", g, synth.GridParams(cell_size=0.5))
     x = torch.full((1000,), 0.5, dtype=torch.float64, device="cuda")
     ws = gp.new_workspace(grid, 10, "mixed")

@@ -80,6 +80,27 @@ def test_mix_equals_alone(setup, graphs):
     srv.close()
 
 
+def test_prestaged_grid_in_the_mix(setup):
+    """A P2P grid with build-time segment records serves the same results, through the
+    captured graphs of its own kernel, as the plain grid's requests alone."""
+    gp, g3, g4, reqs, alone = setup
+    print("serving with a prestaged P2P grid", flush=True)
+    geom4 = synth.config4_geometry(n_lines=20_000, seed_salt=1)
+    g4p = gp.gp_build_grid("p2p", geom4, synth.GridParams(cell_size=100.0, radius_D=100.0,
+                                                          nx=400, ny=400, prestage=1))
+    srv = gp.Server(g3, g4p, n_slots=4, slot_points=65536, mem_budget=4 << 30,
+                    precision="mixed", inputs_on_device=True, use_graphs=True)
+    outs = outputs_for(reqs)
+    for rep in range(2):
+        tickets = [srv.submit(k, x, y, o[0], o[1]) for (k, x, y), o in zip(reqs, outs)]
+        for t in tickets:
+            srv.wait(t)
+        torch.cuda.synchronize()
+        check_same(alone, outs)
+    assert srv.stats()["graph_replays"] > 0
+    srv.close()
+
+
 def test_host_inputs_and_tight_budget(setup):
     gp, g3, g4, reqs, alone = setup
     print("serving host inputs, one slot", flush=True)
