@@ -10,7 +10,7 @@ in the mixed-precision form.  The grids (MBBs, rasterised candidate lists) are b
 once per geometry set and stay resident, as in a serving deployment; their build time
 is reported separately.  Inputs are resident in HBM before the timed region starts.
 
-Printed: ONE JSON line (rank 0).  Multi-GPU runs are not supported by this build.
+Printed: ONE JSON line (rank 0).  Runs on one GPU; --gpus above 1 exits.
 """
 from __future__ import annotations
 
@@ -285,8 +285,9 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the design for sharding points across GPUs is described in DESIGN.md)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (every "
+              "point's result depends only on the point and the resident grid, so points "
+              "would be split across GPUs by cell, each GPU holding the whole grid)",
               file=sys.stderr)
         sys.exit(2)
 

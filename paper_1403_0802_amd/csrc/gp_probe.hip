@@ -1,7 +1,7 @@
 // Measurement probes for the roofline: sustained vector FP32 / FP64 FMA rate (FP32 with
 // VGPR operands and with an SGPR operand), LDS broadcast-read rate, and the P2P
 // inner-loop instruction mix on register data.  Used by
-// bench.py to report the peaks the refinement kernels are judged against; not part of
+// bench.py to report the peaks the refinement kernels are measured against; not part of
 // the join itself.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
