@@ -390,8 +390,35 @@ def pin_tessellation(lib, seed=11):
         assert any(exact.inside_exact(px[i], py[i], [h]) for h in holes), (px[i], py[i])
 
 
+def check_golden(lib, name, cs=None):
+    """One hand-written closed-form fixture of tests/golden/ (brute force when ``cs`` is
+    None, else through the oracle's grid with cells of ``cs`` and a derived extent)."""
+    from tests import golden_cases
+    c = golden_cases.load(name)
+    grid = None
+    if cs is not None:
+        grid = oracle.build_grid(c.geom, GridParams(cell_size=cs, radius_D=c.radius), lib)
+    if c.kind == "pip":
+        got = oracle.pip(c.geom, c.px, c.py, grid, lib=lib)
+        bad = np.nonzero(got != c.want_id)[0]
+        assert bad.size == 0, [(name, c.px[i], c.py[i], got[i], c.want_id[i]) for i in bad]
+    else:
+        gid, gd = oracle.p2p(c.geom, c.px, c.py, c.radius, grid, lib=lib)
+        bad = np.nonzero((gid != c.want_id) | (gd != c.want_dist))[0]
+        assert bad.size == 0, [(name, c.px[i], c.py[i], gid[i], gd[i]) for i in bad]
+
+
+def pin_golden(lib):
+    """The hand-written closed-form fixtures (squares with a hole, a triangle, segment
+    distances at exact Pythagorean values, ties and the range boundary)."""
+    from tests import golden_cases
+    for name in golden_cases.ALL:
+        for cs in (None, 1.0, 2.5):
+            check_golden(lib, name, cs)
+
+
 ALL_PINS = [pin_pip_boxes, pin_pip_hole, pin_pip_convex, pin_pip_star_sectors,
             pin_pip_winding_and_exact, pin_pip_grid_equals_brute, pin_p2p_single_segment,
             pin_p2p_symmetries, pin_p2p_lipschitz_and_exact, pin_p2p_brute_exact,
             pin_p2p_ties_and_range, pin_p2p_grid_equals_brute, pin_grid_definition,
-            pin_tessellation]
+            pin_tessellation, pin_golden]

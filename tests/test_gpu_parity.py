@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from paper_1403_0802_amd import synth
-from tests import pins
+from tests import golden_cases, pins
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -144,6 +144,26 @@ def test_p2p_c2(gp, c2, prec):
     say("  stats", st, "max abs distance error", err)
 
 
+@pytest.mark.parametrize("name", golden_cases.ALL)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_golden_fixtures(gp, name, prec):
+    """The hand-written closed-form fixtures of tests/golden/, at two cell sizes, with
+    the default kernel shapes and with few-point items kept point-parallel."""
+    c = golden_cases.load(name)
+    for cs in (1.0, 2.5):
+        for tuning in (None, dict(points_per_lane=2, vp_points=-1),
+                       dict(points_per_lane=4, vp_points=-1)):
+            say("golden", name, prec, cs, tuning)
+            grid = gp.gp_build_grid(c.kind, c.geom, synth.GridParams(cell_size=cs,
+                                                                     radius_D=c.radius))
+            if c.kind == "pip":
+                got = run_gpu(gp, grid, c.px, c.py, prec, tuning=tuning)
+                assert np.array_equal(got, c.want_id), (cs, tuning, got, c.want_id)
+            else:
+                gid, gd = run_gpu(gp, grid, c.px, c.py, prec, tuning=tuning)
+                check_p2p(gid, gd, c.want_id, c.want_dist, prec, f"{name} cs={cs} {tuning}")
+
+
 # ---------------------------------------------------------------------------- tuning
 
 
@@ -186,6 +206,27 @@ def test_results_invariant_under_tuning(gp, kind):
                 assert np.array_equal(r, ref)
             else:
                 assert np.array_equal(r[0], ref[0]) and np.array_equal(r[1], ref[1]), (prec, t)
+
+
+def test_pip_items_of_every_size(gp):
+    """Point density graded across the domain, so that cells hold from a few to
+    hundreds of points: items full at 1, 2 and 4 points per lane and every remainder
+    size (a cell's last item runs with the fewest points per lane that hold it)."""
+    w = synth.config1(n_points=300_000, grid_n=6, seed_salt=5)
+    w.px = w.px ** 2
+    _, want = oracle.run(w)
+    og = oracle.build_grid(w.geom, w.params)
+    npc = np.bincount(oracle.point_cells(og, w.px, w.py) + 1)[1:]
+    say("pip items of every size: points per cell", np.percentile(npc, [5, 50, 95, 100]))
+    assert np.any((npc > 16) & (npc <= 64)) and np.any((npc > 64) & (npc <= 128))
+    assert np.any(npc > 256)
+    grid = gp.gp_build_grid("pip", w.geom, w.params)
+    for prec in ("fp64", "mixed"):
+        for ppl in (1, 2, 4):
+            for vp in (-1, 16):
+                got = run_gpu(gp, grid, w.px, w.py, prec,
+                              tuning=dict(points_per_lane=ppl, vp_points=vp))
+                assert np.array_equal(got, want), (prec, ppl, vp, int(np.sum(got != want)))
 
 
 def test_shuffle_invariance(gp):
