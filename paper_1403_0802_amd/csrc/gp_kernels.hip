@@ -1925,7 +1925,12 @@ __global__ __launch_bounds__(64) void k_pipmix(RefineArgs a, int persistent) {
   const uint32_t n_items = *a.n_items;
   uint32_t it = persistent ? next_item(a) : blockIdx.x;
   while (it < n_items) {
-    pipmix_item<PPL>(a, a.items[it], A, B, G);
+    // A cell's last item holds the remainder of its points: it runs with the fewest
+    // points per lane that hold them, so its idle point slots cost no tests.
+    const Item item = a.items[it];
+    if (PPL >= 4 && item.npts > 64 && item.npts <= 128) pipmix_item<2>(a, item, A, B, G);
+    else if (PPL >= 2 && item.npts <= 64) pipmix_item<1>(a, item, A, B, G);
+    else pipmix_item<PPL>(a, item, A, B, G);
     if (!persistent) break;
     it = next_item(a);
   }
@@ -2050,42 +2055,42 @@ hipError_t launch_refine(gp_kind kind, gp_precision prec, const RefineArgs &a,
 }
 
 // ------------------------------------------------------------------------- FP64 recheck
-// One wavefront per queued point: the point's full result over all candidates of its
-// cell, in FP64 with the definitions' operation order, straight from the edge records.
-// Lanes take the edges of a feature; parity combines by popcount of the crossing
-// ballots (XOR), distance by an exact wave minimum -- both independent of order.
+// Each queued point gets its full result over all candidates of its cell, in FP64 with
+// the definitions' operation order, straight from the edge records.  Threads take the
+// edges of a feature; parity combines by counting odd threads (XOR), distance by an
+// exact wave minimum -- both independent of order.
 
 __device__ __forceinline__ double wave_min_f64(double v) {
   for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, GP_WAVE));
   return v;
 }
 
-__global__ __launch_bounds__(256) void k_recheck_pip(RefineArgs a) {
+// PIP: one workgroup per queued point.  Its threads split each candidate polygon's
+// edges; the polygon's parity is that of the number of threads with an odd count of
+// crossings, so even the longest rings take a few dozen steps per point.
+__global__ __launch_bounds__(1024) void k_recheck_pip(RefineArgs a) {
   const uint32_t nq = *a.rq_count;
-  const uint32_t lane = lane_id();
-  const uint32_t waves = gridDim.x * (blockDim.x / GP_WAVE);
-  for (uint32_t q = blockIdx.x * (blockDim.x / GP_WAVE) + threadIdx.x / GP_WAVE; q < nq;
-       q += waves) {
+  for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
     const uint32_t i = a.rq[q];
     const uint32_t j = a.perm[i], cell = a.skey[i];
     const double2 p = a.xy[i];
-    const double x = p.x, y = p.y;
     int32_t best = -1;
-    for (int32_t k = a.cand_off[cell]; k < a.cand_off[cell + 1] && best < 0; ++k) {
+    for (int32_t k = a.cand_off[cell]; k < a.cand_off[cell + 1]; ++k) {
       const int32_t f = a.cand_id[k];
-      uint32_t odd = 0;
-      for (int32_t e0 = a.eoff[f]; e0 < a.eoff[f + 1]; e0 += GP_WAVE) {
-        const int32_t e = e0 + (int32_t)lane;
-        bool c = false;
-        if (e < a.eoff[f + 1]) {
-          const double4 r = a.edge64[e];
-          c = cross64(x, y, r.x, r.y, r.z - r.x, r.w, r.w - r.y);
-        }
-        odd ^= (uint32_t)__popcll(ballot(c)) & 1u;
+      const int32_t e1 = a.eoff[f + 1];
+      int odd = 0;
+#pragma unroll 4
+      for (int32_t e = a.eoff[f] + (int32_t)threadIdx.x; e < e1; e += (int32_t)blockDim.x) {
+        const double4 r = a.edge64[e];
+        odd ^= cross64(p.x, p.y, r.x, r.y, r.z - r.x, r.w, r.w - r.y) ? 1 : 0;
       }
-      if (odd) best = f;
+      // the count is the same in every thread, so the exit is uniform
+      if (__syncthreads_count(odd) & 1) {
+        best = f;
+        break;
+      }
     }
-    if (lane == 0) a.out_id[j] = best;
+    if (threadIdx.x == 0) a.out_id[j] = best;
   }
 }
 
@@ -2137,9 +2142,9 @@ __global__ __launch_bounds__(256) void k_recheck_p2p(RefineArgs a) {
 }
 
 hipError_t launch_recheck(gp_kind kind, const RefineArgs &a, int num_cu, hipStream_t s) {
-  dim3 grid((unsigned)(num_cu > 0 ? num_cu * 4 : 1024)), block(256);
-  if (kind == GP_PIP) hipLaunchKernelGGL(k_recheck_pip, grid, block, 0, s, a);
-  else hipLaunchKernelGGL(k_recheck_p2p, grid, block, 0, s, a);
+  const unsigned ncu = (unsigned)(num_cu > 0 ? num_cu : 256);
+  if (kind == GP_PIP) hipLaunchKernelGGL(k_recheck_pip, dim3(ncu), dim3(1024), 0, s, a);
+  else hipLaunchKernelGGL(k_recheck_p2p, dim3(ncu * 4), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
