@@ -3,7 +3,7 @@
 One step is one query batch through the whole per-batch path (cell hash, stable sort,
 gather/rebase, work items, refinement, FP64 recheck, output) for BOTH operations:
   PIP  configuration 3: 50M points against 5,000 Voronoi polygons (holes, up to
-       50,000 vertices), grid 1024 x 1024;
+       50,000 vertices), grid 512 x 512 of 1/512 cells (the fastest of the cell-size sweep);
   P2P  configuration 4: 200M points against 200,000 random-walk polylines, D = 100 m,
        grid 400 x 400 of 100 m cells;
 in the mixed-precision form.  The grids (MBBs, rasterised candidate lists) are built
