@@ -103,20 +103,23 @@ def write_traffic(fetch_csv: str, write_csv: str):
 
 
 WORKLOAD_NAME = "C3 PIP 50M pts x 5000 polygons + C4 P2P 200M pts x 200000 polylines, mixed"
+# The grids of the step (the full-size parity tests build the same ones).  PIP: 1/512, the
+# fastest PIP query of the cell-size sweep (bench.py --cell-sweep).  P2P: 100 m cells with
+# build-time segment records (p2p_prestage), an index structure like the candidate lists;
+# detail.p2p_plain_grid runs the grid without them.
+PIP_GRID = dict(cell_size=1 / 512, nx=512, ny=512)
+P2P_GRID = dict(cell_size=100.0, radius_D=100.0, nx=400, ny=400, prestage=1)
 
 
 def build_workloads(scale: float):
     from paper_1403_0802_amd import synth
     t0 = time.time()
     geom3, info3 = synth.config3_geometry()
-    # 1/512: the fastest PIP query of the cell-size sweep (bench.py --cell-sweep)
-    p3 = synth.GridParams(cell_size=1 / 512, nx=512, ny=512)
+    p3 = synth.GridParams(**PIP_GRID)
     n3 = int(50_000_000 * scale)
     px3, py3 = synth.config3_points(n3)
     geom4 = synth.config4_geometry()
-    # the P2P grid carries its build-time segment records (p2p_prestage), an index
-    # structure like the candidate lists; detail.p2p_plain_grid runs the grid without them
-    p4 = synth.GridParams(cell_size=100.0, radius_D=100.0, nx=400, ny=400, prestage=1)
+    p4 = synth.GridParams(**P2P_GRID)
     n4 = int(200_000_000 * scale)
     px4, py4 = synth.config4_points(n4)
     log(f"[bench] inputs generated in {time.time() - t0:.1f}s: C3 {n3} pts / "

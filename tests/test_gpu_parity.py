@@ -8,6 +8,7 @@ import math
 import numpy as np
 import pytest
 
+import bench
 import oracle
 from paper_1403_0802_amd import synth
 from tests import golden_cases, pins
@@ -765,14 +766,18 @@ def _device_run(gp, grid, x, y, prec):
     return r
 
 
-def test_c3_full_size_50m(gp, c3_geom):
-    """Configuration 3 at its full 50M points, default launch configuration: the mixed
-    ids equal the FP64 ids on every point (compared on the device), and 20,000 sampled
-    points equal the oracle."""
+@pytest.mark.parametrize("grid_kind", ["bench", "cells_1024"])
+def test_c3_full_size_50m(gp, c3_geom, grid_kind):
+    """Configuration 3 at its full 50M points, default launch configuration, on the
+    bench's grid (cells of 1/512) and on cells of 1/1024: the mixed ids equal the FP64 ids
+    on every point (compared on the device), and 20,000 sampled points equal the oracle."""
     geom, _ = c3_geom
-    say("c3 full size: 50M points")
+    say("c3 full size: 50M points,", grid_kind)
     px, py = synth.config3_points(50_000_000)
-    params = synth.GridParams(cell_size=1 / 1024, nx=1024, ny=1024)
+    if grid_kind == "bench":
+        params, want_tests = synth.GridParams(**bench.PIP_GRID), 31_697_377_099
+    else:
+        params, want_tests = synth.GridParams(cell_size=1 / 1024, nx=1024, ny=1024), 28_869_883_377
     grid = gp.gp_build_grid("pip", geom, params)
     x, y = dev_arrays(px, py)
     g64, s64 = _device_run(gp, grid, x, y, "fp64")
@@ -781,18 +786,22 @@ def test_c3_full_size_50m(gp, c3_geom):
     idx = np.random.default_rng(30).choice(len(px), 20_000, replace=False)
     want = oracle.pip(geom, px[idx], py[idx], oracle.build_grid(geom, params))
     assert np.array_equal(gmx.cpu().numpy()[idx], want)
-    assert smx["tests"] == s64["tests"] == 28_869_883_377
+    assert smx["tests"] == s64["tests"] == want_tests
     say("  mixed", smx)
 
 
-def test_c4_full_size_200m(gp):
-    """Configuration 4 at its full 200M points, default launch configuration: mixed ids
-    and distances equal the FP64 form's on every point (compared on the device), and
-    20,000 sampled points equal the oracle."""
-    say("c4 full size: 200M points")
+@pytest.mark.parametrize("grid_kind", ["bench", "no_records"])
+def test_c4_full_size_200m(gp, grid_kind):
+    """Configuration 4 at its full 200M points, default launch configuration, on the
+    bench's grid (build-time segment records: the kernel the bench times) and on the same
+    grid without records: mixed ids and distances equal the FP64 form's on every point
+    (compared on the device), and 20,000 sampled points equal the oracle."""
+    say("c4 full size: 200M points,", grid_kind)
     geom = synth.config4_geometry()
     px, py = synth.config4_points(200_000_000)
-    params = synth.GridParams(cell_size=100.0, radius_D=100.0, nx=400, ny=400)
+    params = synth.GridParams(**bench.P2P_GRID)
+    if grid_kind == "no_records":
+        params.prestage = 0
     grid = gp.gp_build_grid("p2p", geom, params)
     x, y = dev_arrays(px, py)
     i64, d64, s64 = _device_run(gp, grid, x, y, "fp64")
