@@ -1244,6 +1244,27 @@ __device__ void pipmix_item(const RefineArgs &a, const Item it, float4 *ldsA, fl
       }
       __syncthreads();
       uint32_t t = 0;
+      // eight or four edges per step: their LDS reads are in flight together, so a wave
+      // waits on the LDS once per 8 * PPL (4 * PPL) tests
+      for (; t + 8 <= nA; t += 8) {
+        float4 e[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) e[q] = ldsA[t + q];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+          uint64_t m = 0;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) m ^= plain_cross(px[j], py[j], e[q]);
+          par[j] ^= m;
+        }
+      }
+      for (; t + 4 <= nA; t += 4) {
+        const float4 e0 = ldsA[t], e1 = ldsA[t + 1], e2 = ldsA[t + 2], e3 = ldsA[t + 3];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j)
+          par[j] ^= plain_cross(px[j], py[j], e0) ^ plain_cross(px[j], py[j], e1) ^
+                    plain_cross(px[j], py[j], e2) ^ plain_cross(px[j], py[j], e3);
+      }
       for (; t + 2 <= nA; t += 2) {
         const float4 e0 = ldsA[t], e1 = ldsA[t + 1];
 #pragma unroll
@@ -1255,9 +1276,7 @@ __device__ void pipmix_item(const RefineArgs &a, const Item it, float4 *ldsA, fl
 #pragma unroll
         for (int j = 0; j < PPL; ++j) par[j] ^= plain_cross(px[j], py[j], e0);
       }
-      for (t = 0; t < nB; ++t) {
-        const float4 e = ldsB[t];
-        const float G = ldsG[t];
+      auto guarded = [&](const float4 e, const float G) {
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
           const float ty = py[j] - e.y;
@@ -1267,7 +1286,14 @@ __device__ void pipmix_item(const RefineArgs &a, const Item it, float4 *ldsA, fl
           par[j] ^= st & ballot(d > 0.0f);
           flg[j] |= (eq & ballot(!(d < -G))) | (st & ballot(!(fabsf(d) > G)));
         }
+      };
+      for (t = 0; t + 2 <= nB; t += 2) {  // two edges per step, reads in flight together
+        const float4 ea = ldsB[t], eb = ldsB[t + 1];
+        const float Ga = ldsG[t], Gb = ldsG[t + 1];
+        guarded(ea, Ga);
+        guarded(eb, Gb);
       }
+      if (t < nB) guarded(ldsB[t], ldsG[t]);
     }
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
