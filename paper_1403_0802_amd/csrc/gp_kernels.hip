@@ -175,7 +175,7 @@ hipError_t launch_exclusive_scan_u32(const uint32_t *in, uint32_t *out, size_t n
 
 // ------------------------------------------------------------------------- radix sort
 // Stable LSD radix sort of (uint32 key, uint32 value[, FP64 (x, y) payload]) records.
-// Digits are at most 10 bits wide and the pass count is the least that covers the key
+// Digits are at most 8 bits wide and the pass count is the least that covers the key
 // width.  Each pass: per-tile digit histogram, exclusive scan of the digit-major
 // histogram, then a stable scatter in which every key's rank among equal digits of its
 // tile comes from wavefront ballots (peer masks), not from atomics, so the output
