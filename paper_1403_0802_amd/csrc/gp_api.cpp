@@ -61,14 +61,22 @@ struct DevBuf {
 }  // namespace
 
 // Defaults from full-size sweeps on the configuration-3/4 workloads (gp_autotune
-// re-tunes): mixed P2P 4 points per lane, mixed PIP 2 (its per-item edge staging is
-// shared by 128 points), FP64 forms 1.
+// re-tunes): P2P 4 points per lane from a persistent queue (the FP64 form with 64-segment
+// chunks: its 64-byte LDS records otherwise limit the waves per CU), PIP 2 points per lane
+// and one workgroup per item (the per-item edge staging is shared by 128 points).
 static gp_tuning default_tuning(gp_kind kind, gp_precision prec) {
   gp_tuning t;
-  t.points_per_lane = prec == GP_MIXED ? (kind == GP_P2P ? 4 : 2) : 1;
-  t.edge_chunk = prec == GP_MIXED ? 128 : 256;
-  t.wg_per_cu = (prec == GP_MIXED && kind == GP_P2P) ? 32 : 16;
-  t.persistent = (prec == GP_MIXED && kind == GP_PIP) ? 0 : 1;
+  if (kind == GP_P2P) {
+    t.points_per_lane = 4;
+    t.edge_chunk = prec == GP_MIXED ? 128 : 64;
+    t.wg_per_cu = 32;
+    t.persistent = 1;
+  } else {
+    t.points_per_lane = 2;
+    t.edge_chunk = 128;
+    t.wg_per_cu = 16;
+    t.persistent = 0;
+  }
   t.waves_per_item = 1;
   t.vp_points = kind == GP_PIP ? 16 : -1;
   return t;
