@@ -261,8 +261,8 @@ def cell_sweep(gp, torch, dev, c3, c4):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the point counts")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -398,11 +398,13 @@ def main():
     traffic = load_traffic(dom_kernel, workload)
     detail = {
         "pip": {"points": x3.numel(), "tests": tests_pip, "ms": avg(st_pip, "ms_total"),
+                "points_per_s": x3.numel() / (avg(st_pip, "ms_total") / 1e3),
                 "ms_pairing": avg(st_pip, "ms_pairing"), "ms_refine": pip_ref,
                 "ms_recheck": avg(st_pip, "ms_recheck"), "n_rechecked": st_pip[0]["n_rechecked"],
                 "n_items": st_pip[0]["n_items"], "refine_tflops": pip_flops / 1e12,
                 "refine_frac_fp32": pip_flops / FP32_PEAK},
         "p2p": {"points": x4.numel(), "tests": tests_p2p, "ms": avg(st_p2p, "ms_total"),
+                "points_per_s": x4.numel() / (avg(st_p2p, "ms_total") / 1e3),
                 "ms_pairing": avg(st_p2p, "ms_pairing"), "ms_refine": p2p_ref,
                 "ms_recheck": avg(st_p2p, "ms_recheck"), "n_rechecked": st_p2p[0]["n_rechecked"],
                 "n_items": st_p2p[0]["n_items"], "refine_tflops": p2p_flops / 1e12,
