@@ -328,18 +328,18 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if not args.no_autotune:
-        # The autotuner times each kernel configuration on a sample of the workload.  The
-        # sample keeps every point of one cell in 16 (cells whose column and row are both
-        # multiples of 4), so points per cell -- what the tile shape trades against -- are
-        # those of the full workload.
+        # The autotuner times each kernel configuration.  PIP queries take milliseconds,
+        # so it tunes on the full workload.  For P2P it tunes on a sample that keeps
+        # every point of one cell in 16 (cells whose column and row are both multiples
+        # of 4), so points per cell -- what the tile shape trades against -- are those
+        # of the full workload.
         def cell_sample(x, y, p):
             cx = torch.floor((x - p.x0) / p.cell_size).to(torch.int64)
             cy = torch.floor((y - p.y0) / p.cell_size).to(torch.int64)
             m = (cx % 4 == 0) & (cy % 4 == 0)
             return x[m].contiguous(), y[m].contiguous()
-        sx, sy = cell_sample(x3, y3, p3)
-        log("[bench] autotune pip on", sx.numel(), "points",
-            gp.gp_autotune(grid3, prec, sx, sy, ws3))
+        log("[bench] autotune pip on", x3.numel(), "points",
+            gp.gp_autotune(grid3, prec, x3, y3, ws3))
         sx, sy = cell_sample(x4, y4, p4)
         log("[bench] autotune p2p on", sx.numel(), "points",
             gp.gp_autotune(grid4, prec, sx, sy, ws4))
