@@ -15,6 +15,7 @@ Printed: ONE JSON line (rank 0).  Runs on one GPU; --gpus above 1 exits.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import math
@@ -240,14 +241,20 @@ def serving_run(gp, torch, grid3, grid4, n_requests: int, precision: str):
             "slots": slots, "slot_points": slot_points}
 
 
-def cell_sweep(gp, torch, dev, c3, c4):
+def cell_sweep(gp, torch, dev, c3, c4, which="both"):
     """The filter-versus-refine trade-off (Sec. III.A): query time, candidate pairs, tests
     and grid memory at five cell sizes around each configuration's default, on the full
-    point sets, mixed form, default kernel tuning."""
+    point sets, mixed form, default kernel tuning; `which` is "pip", "p2p" or "both"."""
     out = {}
     for name, kind, (geom, p, px, py), sizes in (
             ("pip_c3", "pip", c3, [1 / 256, 1 / 512, 1 / 1024, 1 / 2048, 1 / 4096]),
             ("p2p_c4", "p2p", c4, [25.0, 50.0, 100.0, 200.0, 400.0])):
+        if which not in ("both", kind):
+            continue
+        if kind == "p2p":
+            # the sweep is over the filter; build-time segment records (20 B per cell and
+            # candidate segment: about 100 GB at 25 m cells) stay out of it
+            p = dataclasses.replace(p, prestage=0)
         x, y = torch.from_numpy(px).to(dev), torch.from_numpy(py).to(dev)
         t0 = time.perf_counter()
         best, rows = gp.gp_sweep_cell_size(kind, geom, p, sizes, x, y, "mixed")
@@ -276,7 +283,7 @@ def main():
                     help="skip the grid-option measurements (cell classes, segment filter, prestage)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--cell-sweep", action="store_true",
+    ap.add_argument("--cell-sweep", nargs="?", const="both", choices=("pip", "p2p", "both"),
                     help="instead of the step: sweep the cell size of both grids on the full "
                          "workloads (gp_sweep_cell_size) and print one JSON line")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -303,7 +310,7 @@ def main():
     geom3, p3, px3, py3 = c3
     geom4, p4, px4, py4 = c4
     if args.cell_sweep:
-        cell_sweep(gp, torch, dev, c3, c4)
+        cell_sweep(gp, torch, dev, c3, c4, args.cell_sweep)
         return
     t0 = time.perf_counter()
     grid3 = gp.gp_build_grid("pip", geom3, p3)
