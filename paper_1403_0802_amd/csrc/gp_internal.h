@@ -28,7 +28,8 @@ struct RefineArgs {
   // work queue
   const Item *items;
   const uint32_t *n_items;   // device scalar written by the item builder
-  uint32_t *item_counter;    // device scalar, zeroed before the launch
+  uint32_t *item_counter;    // [GP_XCDS] device counters of the item queues, zeroed before
+                             // the launch
   // grid
   const int32_t *cand_off;   // [ncells+1]
   const int32_t *cand_id;    // [npairs]
@@ -117,7 +118,8 @@ struct Workspace {
   size_t bytes;
 };
 
-enum Counter { C_ITEM = 0, C_RQ = 1, C_NITEMS = 2, C_NPAIRED = 3, C_COUNT = 16 };
+// C_ITEM .. C_ITEM + GP_XCDS - 1: the item queues of the persistent launches, one per XCD.
+enum Counter { C_RQ = 1, C_NITEMS = 2, C_NPAIRED = 3, C_ITEM = 8, C_COUNT = 16 };
 
 size_t workspace_layout(const Grid &g, int64_t n, gp_precision prec, void *base, Workspace *ws);
 size_t scan_tmp_elems(size_t n);

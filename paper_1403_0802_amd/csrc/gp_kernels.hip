@@ -26,6 +26,8 @@
 namespace gp {
 
 #define GP_WAVE 64
+#define GP_XCDS 8     // XCDs of an MI355X, each with its own L2
+#define GP_XBLOCK 32  // consecutive work items per block of an XCD's queue
 #define SCAN_THREADS 256
 #define SCAN_ITEMS 16
 #define SCAN_TILE (SCAN_THREADS * SCAN_ITEMS)
@@ -981,9 +983,28 @@ __device__ __forceinline__ double seg_d2_64(double px, double py, double ax, dou
 
 // ------------------------------------------------------------------------- work queue
 
-__device__ __forceinline__ uint32_t next_item(const RefineArgs &a) {
+// Work queue of the persistent launches, with XCD locality.  Items come in cell order;
+// blocks of GP_XBLOCK consecutive items go round-robin to GP_XCDS queues, and a
+// workgroup pops from the queue of its XCD (workgroups are placed on the XCDs
+// round-robin by index), so the items of one cell share an L2 and its staged edges or
+// segment records are fetched from HBM once.  A workgroup whose queue is exhausted takes
+// items from the next queues: every item is handed out exactly once, and each pop ends
+// after at most GP_XCDS exhausted queues.  Returns n_items when nothing is left.
+__device__ __forceinline__ uint32_t pop_item(const RefineArgs &a, uint32_t n_items) {
+  const uint32_t home = blockIdx.x % GP_XCDS;
+  for (uint32_t k = 0; k < GP_XCDS; ++k) {
+    const uint32_t q = (home + k) % GP_XCDS;
+    const uint32_t c = atomicAdd(a.item_counter + q, 1u);
+    // the c-th item of queue q; increasing in c, so the first miss exhausts the queue
+    const uint64_t it = ((uint64_t)(c / GP_XBLOCK) * GP_XCDS + q) * GP_XBLOCK + c % GP_XBLOCK;
+    if (it < n_items) return (uint32_t)it;
+  }
+  return n_items;
+}
+
+__device__ __forceinline__ uint32_t next_item(const RefineArgs &a, uint32_t n_items) {
   uint32_t it = 0;
-  if (lane_id() == 0) it = atomicAdd(a.item_counter, 1u);
+  if (lane_id() == 0) it = pop_item(a, n_items);
   return uniform(it);
 }
 
@@ -1934,11 +1955,11 @@ __global__ __launch_bounds__(64) void k_pip64(RefineArgs a, int persistent) {
   extern __shared__ __align__(16) unsigned char smem[];
   PipRec64 *lds = (PipRec64 *)smem;
   const uint32_t n_items = *a.n_items;
-  uint32_t it = persistent ? next_item(a) : blockIdx.x;
+  uint32_t it = persistent ? next_item(a, n_items) : blockIdx.x;
   while (it < n_items) {
     pip64_item<PPL>(a, a.items[it], lds);
     if (!persistent) break;
-    it = next_item(a);
+    it = next_item(a, n_items);
   }
 }
 
@@ -1949,7 +1970,7 @@ __global__ __launch_bounds__(64) void k_pipmix(RefineArgs a, int persistent) {
   float4 *B = A + a.edge_chunk;
   float *G = (float *)(B + a.edge_chunk);
   const uint32_t n_items = *a.n_items;
-  uint32_t it = persistent ? next_item(a) : blockIdx.x;
+  uint32_t it = persistent ? next_item(a, n_items) : blockIdx.x;
   while (it < n_items) {
     // A cell's last item holds the remainder of its points: it runs with the fewest
     // points per lane that hold them, so its idle point slots cost no tests.
@@ -1958,14 +1979,15 @@ __global__ __launch_bounds__(64) void k_pipmix(RefineArgs a, int persistent) {
     else if (PPL >= 2 && item.npts <= 64) pipmix_item<1>(a, item, A, B, G);
     else pipmix_item<PPL>(a, item, A, B, G);
     if (!persistent) break;
-    it = next_item(a);
+    it = next_item(a, n_items);
   }
 }
 
 // Work-queue pop for a workgroup of several waves (broadcast through LDS).
-__device__ __forceinline__ uint32_t next_item_wg(const RefineArgs &a, uint32_t *slot) {
+__device__ __forceinline__ uint32_t next_item_wg(const RefineArgs &a, uint32_t n_items,
+                                                 uint32_t *slot) {
   __syncthreads();
-  if (threadIdx.x == 0) *slot = atomicAdd(a.item_counter, 1u);
+  if (threadIdx.x == 0) *slot = pop_item(a, n_items);
   __syncthreads();
   return *slot;
 }
@@ -1977,11 +1999,13 @@ __global__ __launch_bounds__(64 * W) void k_p2p64(RefineArgs a, int persistent) 
   SegRec64 *lds = (SegRec64 *)smem;
   int2 *tab = (int2 *)(lds + a.edge_chunk);
   const uint32_t n_items = *a.n_items;
-  uint32_t it = persistent ? (W == 1 ? next_item(a) : next_item_wg(a, &s_item)) : blockIdx.x;
+  uint32_t it = persistent ? (W == 1 ? next_item(a, n_items)
+                                      : next_item_wg(a, n_items, &s_item))
+                           : blockIdx.x;
   while (it < n_items) {
     p2p64_item<PPL, W>(a, a.items[it], lds, tab);
     if (!persistent) break;
-    it = W == 1 ? next_item(a) : next_item_wg(a, &s_item);
+    it = W == 1 ? next_item(a, n_items) : next_item_wg(a, n_items, &s_item);
   }
 }
 
@@ -1998,11 +2022,13 @@ __device__ __forceinline__ void p2pmix_loop(const RefineArgs &a, int persistent)
   int *slotseg = (int *)(tab + a.edge_chunk);
   int *slotf = slotseg + a.edge_chunk;
   const uint32_t n_items = *a.n_items;
-  uint32_t it = persistent ? (W == 1 ? next_item(a) : next_item_wg(a, &s_item)) : blockIdx.x;
+  uint32_t it = persistent ? (W == 1 ? next_item(a, n_items)
+                                      : next_item_wg(a, n_items, &s_item))
+                           : blockIdx.x;
   while (it < n_items) {
     p2pmix_item<PPL, W, PRE>(a, a.items[it], U, V, tab, slotseg, slotf, red, smem);
     if (!persistent) break;
-    it = W == 1 ? next_item(a) : next_item_wg(a, &s_item);
+    it = W == 1 ? next_item(a, n_items) : next_item_wg(a, n_items, &s_item);
   }
 }
 
