@@ -244,6 +244,25 @@ def test_shuffle_invariance(gp):
 # ---------------------------------------------------------------------------- edge cases
 
 
+def test_item_queues_few_and_many_items(gp):
+    """The persistent launches' per-XCD item queues hand out every item exactly once,
+    whether there are far fewer items than workgroups, item counts just off the queues'
+    block size, or many items per queue (P2P, both forms, one and four waves per item)."""
+    w = synth.config2(n_points=300_000, n_lines=4_000, seed_salt=6)
+    grid = gp.gp_build_grid("p2p", w.geom, w.params)
+    for n in (1, 5, 257, 31 * 256 + 7, 300_000):
+        px, py = w.px[:n], w.py[:n]
+        want_id, want_d = oracle.p2p(w.geom, px, py, w.params.radius_D,
+                                     oracle.build_grid(w.geom, w.params))
+        for prec in ("fp64", "mixed"):
+            for t in (dict(points_per_lane=1, wg_per_cu=32, persistent=1),
+                      dict(points_per_lane=4, wg_per_cu=1, persistent=1),
+                      dict(points_per_lane=1, wg_per_cu=8, persistent=1, waves_per_item=4)):
+                gid, gd, st = run_gpu(gp, grid, px, py, prec, stats=True, tuning=t)
+                say("  queues", n, prec, t, "items", st["n_items"])
+                check_p2p(gid, gd, want_id, want_d, prec, f"queues n={n} {prec} {t}")
+
+
 def test_empty_and_unpaired_inputs(gp):
     say("empty / unpaired")
     w = synth.config1(n_points=10, grid_n=4)
