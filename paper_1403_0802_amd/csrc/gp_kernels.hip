@@ -2026,7 +2026,16 @@ __device__ __forceinline__ void p2pmix_loop(const RefineArgs &a, int persistent)
                                       : next_item_wg(a, n_items, &s_item))
                            : blockIdx.x;
   while (it < n_items) {
-    p2pmix_item<PPL, W, PRE>(a, a.items[it], U, V, tab, slotseg, slotf, red, smem);
+    // A cell's last item holds the remainder of its points: with one wave per item it
+    // runs with the fewest points per lane that hold them, so its idle point slots cost
+    // no tests.
+    const Item item = a.items[it];
+    if (W == 1 && PPL >= 4 && item.npts <= 128 && item.npts > 64)
+      p2pmix_item<2, W, PRE>(a, item, U, V, tab, slotseg, slotf, red, smem);
+    else if (W == 1 && PPL >= 2 && item.npts <= 64)
+      p2pmix_item<1, W, PRE>(a, item, U, V, tab, slotseg, slotf, red, smem);
+    else
+      p2pmix_item<PPL, W, PRE>(a, item, U, V, tab, slotseg, slotf, red, smem);
     if (!persistent) break;
     it = W == 1 ? next_item(a, n_items) : next_item_wg(a, n_items, &s_item);
   }
