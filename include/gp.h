@@ -133,7 +133,9 @@ typedef struct gp_tuning {
     int32_t points_per_lane; /* 1, 2 or 4: a work item holds up to 64*ppl points */
     int32_t edge_chunk;      /* edges staged in LDS per round: 64..512, multiple of 64 */
     int32_t wg_per_cu;       /* persistent workgroups per compute unit: 1..32 */
-    int32_t persistent;      /* 1: persistent work queue; 0: one workgroup per item */
+    int32_t persistent;      /* 1: persistent workgroups popping items from one queue per
+                                XCD (stealing from the others when theirs is empty);
+                                0: one workgroup per item */
     int32_t waves_per_item;  /* P2P: 1, 2 or 4 wavefronts share one LDS staging and a work
                                 item holds up to 64*ppl*waves points; PIP: always 1 */
     int32_t vp_points;       /* PIP: items with at most this many points (1..64) use the
