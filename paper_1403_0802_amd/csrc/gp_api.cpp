@@ -135,6 +135,22 @@ static float half_box(const Grid &g) {
 // within D + T.
 static float p2p_margin(const Grid &g) { return (float)std::max(0.01 * g.D, g.cs * 0x1p-10); }
 
+// 64-bit sum of the n per-feature pair counts at cnt (device); -1 (with the error set)
+// when a HIP call fails.  Synchronises the stream.
+static int64_t pair_total(const uint32_t *cnt, size_t n, hipStream_t s) {
+  DevBuf d_sum;
+  unsigned long long total = 0;
+  hipError_t e = d_sum.alloc(16);
+  if (e == hipSuccess) e = launch_sum_u32(cnt, n, (unsigned long long *)d_sum.p, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&total, d_sum.p, 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    set_error(GP_E_HIP, "pair count failed: %s", hipGetErrorString(e));
+    return -1;
+  }
+  return total > (unsigned long long)INT64_MAX ? INT64_MAX : (int64_t)total;
+}
+
 extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
                                    const gp_grid_params *params, void *hip_stream,
                                    gp_grid **out) {
@@ -319,13 +335,15 @@ extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
     GP_TRY_HIP_G(d_tmp.alloc(scan_tmp_elems(std::max(nfe, (size_t)ncells + 1)) * 4));
     GP_TRY_HIP_G(launch_raster_count(d_mbb.as<double>(), (int32_t)nf, x0, y0, cs, g->nx, g->ny,
                                      d_cnt.as<uint32_t>(), s));
+    // the total in 64 bits first: the 32-bit scan below wraps once it passes 2^32
+    const int64_t total = pair_total(d_cnt.as<uint32_t>(), (size_t)nf, s);
+    if (total < 0) return fail(GP_E_HIP);
+    if (total >= kMaxCount)
+      return fail(set_error(GP_E_CAPACITY, "%lld (cell, feature) pairs exceed 2^31 - 1",
+                            (long long)total));
     GP_TRY_HIP_G(launch_exclusive_scan_u32(d_cnt.as<uint32_t>(), d_cnt.as<uint32_t>(), nfe,
                                            d_tmp.as<uint32_t>(), s));
-    uint32_t npairs = 0;
-    GP_TRY_HIP_G(hipMemcpyAsync(&npairs, d_cnt.as<uint32_t>() + nf, 4, hipMemcpyDeviceToHost, s));
-    GP_TRY_HIP_G(hipStreamSynchronize(s));
-    if (npairs >= (uint32_t)kMaxCount)
-      return fail(set_error(GP_E_CAPACITY, "too many (cell, feature) pairs"));
+    const uint32_t npairs = (uint32_t)total;
     g->npairs = (int32_t)npairs;
     DevBuf kA, kB, vA, vB, hist, stmp;
     const size_t np = std::max<size_t>(npairs, 1);
@@ -395,13 +413,14 @@ extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
     GP_TRY_HIP_G(launch_seg_boxes(g->d_edge64, ns, D, cs * 0x1p-20, box.as<double>(), s));
     GP_TRY_HIP_G(launch_raster_count(box.as<double>(), ns, x0, y0, cs, g->nx, g->ny,
                                      cnt.as<uint32_t>(), s));
+    const int64_t total = pair_total(cnt.as<uint32_t>(), (size_t)ns, s);
+    if (total < 0) return fail(GP_E_HIP);
+    if (total >= kMaxCount)
+      return fail(set_error(GP_E_CAPACITY, "%lld (cell, segment) pairs exceed 2^31 - 1",
+                            (long long)total));
     GP_TRY_HIP_G(launch_exclusive_scan_u32(cnt.as<uint32_t>(), cnt.as<uint32_t>(),
                                            (size_t)ns + 1, tmp.as<uint32_t>(), s));
-    uint32_t np2 = 0;
-    GP_TRY_HIP_G(hipMemcpyAsync(&np2, cnt.as<uint32_t>() + ns, 4, hipMemcpyDeviceToHost, s));
-    GP_TRY_HIP_G(hipStreamSynchronize(s));
-    if (np2 >= (uint32_t)kMaxCount)
-      return fail(set_error(GP_E_CAPACITY, "too many (cell, segment) pairs"));
+    const uint32_t np2 = (uint32_t)total;
     g->ncseg = np2;
     const size_t n2 = std::max<size_t>(np2, 1);
     DevBuf kA, kB, vA, vB, hist, stmp;

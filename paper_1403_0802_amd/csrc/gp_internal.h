@@ -153,6 +153,8 @@ hipError_t launch_mbb(const int32_t *ring_vert_off, const int32_t *feature_ring_
 hipError_t launch_extent(const double *mbb, int32_t nf, double *out4, hipStream_t s);
 hipError_t launch_raster_count(const double *mbb, int32_t nf, double x0, double y0, double cs,
                                int32_t nx, int32_t ny, uint32_t *cnt, hipStream_t s);
+// out[0] = sum of v[0..n) in 64 bits (out is zeroed first).
+hipError_t launch_sum_u32(const uint32_t *v, size_t n, unsigned long long *out, hipStream_t s);
 hipError_t launch_raster_emit(const double *mbb, int32_t nf, double x0, double y0, double cs,
                               int32_t nx, int32_t ny, const uint32_t *off, uint32_t *pair_cell,
                               uint32_t *pair_fid, hipStream_t s);

@@ -608,6 +608,25 @@ hipError_t launch_raster_count(const double *mbb, int32_t nf, double x0, double 
   return hipGetLastError();
 }
 
+// 64-bit total of n u32 counts (the (cell, feature) pair count before the 32-bit scan:
+// a per-feature count is at most the grid's 2^28 cells, but their sum may pass 2^32).
+__global__ __launch_bounds__(256) void k_sum_u32(const uint32_t *v, size_t n,
+                                                 unsigned long long *out) {
+  unsigned long long t = 0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    t += v[i];
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, GP_WAVE);
+  if (lane_id() == 0 && t) atomicAdd(out, t);
+}
+
+hipError_t launch_sum_u32(const uint32_t *v, size_t n, unsigned long long *out, hipStream_t s) {
+  hipError_t e = launch_fill_u32((uint32_t *)out, 0u, 2, s);
+  if (e != hipSuccess || n == 0) return e;
+  hipLaunchKernelGGL(k_sum_u32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, v, n, out);
+  return hipGetLastError();
+}
+
 // The cells every segment's box reaches (the rasteriser's ranges of seg_box, so exactly
 // the cells a segment list would hold it in): (x lo, x hi, y lo, y hi), empty when the
 // box misses the grid.

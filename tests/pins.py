@@ -390,6 +390,32 @@ def pin_tessellation(lib, seed=11):
         assert any(exact.inside_exact(px[i], py[i], [h]) for h in holes), (px[i], py[i])
 
 
+def pin_pip_count_overlaps(lib, seed=12):
+    """Overlapping boxes, one of them with a hole: the number of polygons whose even-odd
+    test holds is the sum of the half-open box indicators, so points count 0 to 4
+    (dyadic inputs: every operation is sign-exact, boundaries included)."""
+    boxes = [(0.0, 0.0, 4.0, 4.0), (2.0, 2.0, 6.0, 6.0), (3.0, 1.0, 5.0, 5.0),
+             (-1.0, 3.0, 7.0, 3.5)]
+    hole = (3.5, 3.5, 4.5, 4.5)  # a hole in the third box
+    feats = [[box(*b)] for b in boxes]
+    feats[2].append(box(*hole, ccw=False))
+    g = polygons(feats)
+    grid = np.arange(-12, 61) / 8.0
+    px, py = np.meshgrid(grid, grid)
+    px, py = px.ravel(), py.ravel()
+    rng = np.random.default_rng(seed)
+    px = np.concatenate([px, rng.uniform(-1.5, 7.5, 5000)])
+    py = np.concatenate([py, rng.uniform(-1.5, 7.5, 5000)])
+
+    def ind(b):
+        return (b[0] <= px) & (px < b[2]) & (b[1] <= py) & (py < b[3])
+
+    want = sum(ind(b).astype(np.int32) for b in boxes) - (ind(boxes[2]) & ind(hole))
+    got = oracle.pip_count(g, px, py, lib=lib)
+    assert np.array_equal(got, want), np.sum(got != want)
+    assert want.max() == 4 and np.sum(want == 2) > 100 and np.sum(want == 3) > 10
+
+
 def check_golden(lib, name, cs=None):
     """One hand-written closed-form fixture of tests/golden/ (brute force when ``cs`` is
     None, else through the oracle's grid with cells of ``cs`` and a derived extent)."""
@@ -421,4 +447,4 @@ ALL_PINS = [pin_pip_boxes, pin_pip_hole, pin_pip_convex, pin_pip_star_sectors,
             pin_pip_winding_and_exact, pin_pip_grid_equals_brute, pin_p2p_single_segment,
             pin_p2p_symmetries, pin_p2p_lipschitz_and_exact, pin_p2p_brute_exact,
             pin_p2p_ties_and_range, pin_p2p_grid_equals_brute, pin_grid_definition,
-            pin_tessellation, pin_golden]
+            pin_tessellation, pin_pip_count_overlaps, pin_golden]

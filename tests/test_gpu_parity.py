@@ -731,6 +731,29 @@ def test_grid_and_option_limits(gp):
     assert e.value.status == gp.GP_E_INVALID_ARG
 
 
+def test_pair_totals_beyond_32_bits_are_refused(gp):
+    """The (cell, feature) and (cell, segment) pair totals are summed in 64 bits before
+    the 32-bit scan: totals of 2^31 or more are refused with GP_E_CAPACITY, also when
+    they pass 2^32 and a 32-bit sum would have wrapped to a small value (17 features
+    that each cover all 2^28 cells: 4.56e9 pairs, 2.7e8 after a wrap)."""
+    n = 1 << 14
+    full = synth.GridParams(cell_size=1.0 / n, nx=n, ny=n)
+    for copies in (9, 17):
+        say("pip pair total", copies, "x 2^28")
+        g = pins.polygons([[pins.box(0.0, 0.0, 1.0, 1.0)]] * copies)
+        with pytest.raises(gp.GPError) as e:
+            gp.gp_build_grid("pip", g, full)
+        assert e.value.status == gp.GP_E_CAPACITY, copies
+    say("p2p segment pair total 17 x 2^28")
+    zig = [(float(i % 2), float(i % 2)) for i in range(18)]  # 17 segments across the square
+    g = pins.polylines([zig])
+    with pytest.raises(gp.GPError) as e:
+        gp.gp_build_grid("p2p", g, synth.GridParams(cell_size=1.0 / n, nx=n, ny=n,
+                                                    segment_filter=1))
+    assert e.value.status == gp.GP_E_CAPACITY
+    torch.cuda.synchronize()
+
+
 # ---------------------------------------------------------------------------- scale
 
 

@@ -29,6 +29,10 @@ MUTANTS = [
     ("cell_upper_closed", "fx < (double)nx", "fx <= (double)nx"),
     ("no_expand", "mnx = mnx - D; mny = mny - D;", "mnx = mnx; mny = mny - D;"),
     ("unstable_sort", "perm[pos[c]++] = i;", "perm[pos[c + 1] - 1 - (pos[c]++ - pt_off[c])] = i;"),
+    ("count_first_hit", "cnt += polygon_inside(px[i], py[i], f, fro, rvo, x, y);",
+     "if (polygon_inside(px[i], py[i], f, fro, rvo, x, y)) { cnt = 1; break; }"),
+    ("count_clamped", "cnt += polygon_inside(px[i], py[i], f, fro, rvo, x, y);",
+     "cnt = cnt | polygon_inside(px[i], py[i], f, fro, rvo, x, y);"),
 ]
 
 
