@@ -128,9 +128,13 @@ def build_workloads(scale: float):
     return (geom3, p3, px3, py3), (geom4, p4, px4, py4)
 
 
-def cpu_baseline(c3, c4, budget_s: float):
-    """The CPU oracle as it stands (grid-filtered, FP64, OpenMP over points) on all host
-    threads, on bounded samples of the same workloads."""
+def cpu_baseline(c3, c4, budget_s: float, step_tests):
+    """The CPU oracle as it stands (grid-filtered, FP64, OpenMP over points) on a seeded
+    random sample of each workload's points, with 1 thread (the paper's single-core
+    "SC" setting) and with every host thread ("MC"), median of 3 runs each.  Sample sizes
+    are set from a short calibration run so the twelve runs take about budget_s.  The
+    rate of each setting is that of the step's own mix: step_tests = (PIP tests, P2P
+    tests) of one step, done at the sampled PIP and P2P rates."""
     import oracle
     lib = oracle.load()
     threads = len(os.sched_getaffinity(0))
@@ -138,37 +142,53 @@ def cpu_baseline(c3, c4, budget_s: float):
     geom4, p4, px4, py4 = c4
     g3 = oracle.build_grid(geom3, p3, lib)
     g4 = oracle.build_grid(geom4, p4, lib)
+    rng = np.random.default_rng(14030805)
+    per_run = budget_s / 12.0
     out = {}
-    tests_total = 0
-    secs_total = 0.0
-    for name, geom, g, px, py, start in (("pip", geom3, g3, px3, py3, 20_000),
-                                         ("p2p", geom4, g4, px4, py4, 200_000)):
-        m = start
-        while True:
-            sx, sy = px[:m], py[:m]
+    for name, geom, g, px, py in (("pip", geom3, g3, px3, py3), ("p2p", geom4, g4, px4, py4)):
+        # a seeded random sample (not a prefix), large enough for any run below
+        order = rng.choice(len(px), min(len(px), 8_000_000), replace=False)
+
+        def run(m, nthreads):
+            sx, sy = px[order[:m]], py[order[:m]]
             t0 = time.perf_counter()
             if name == "pip":
-                oracle.pip(geom, sx, sy, g, threads, lib)
+                oracle.pip(geom, sx, sy, g, nthreads, lib)
             else:
-                oracle.p2p(geom, sx, sy, p4.radius_D, g, threads, lib)
-            dt = time.perf_counter() - t0
-            if dt > budget_s / 4 or m >= len(px):
-                break
-            m = min(len(px), int(m * max(2.0, budget_s / 2 / max(dt, 1e-3))))
-        tests = oracle.test_count(g, px[:m], py[:m], lib)
-        out[name] = {"points": m, "tests": tests, "seconds": dt, "tests_per_s": tests / dt}
-        tests_total += tests
-        secs_total += dt
+                oracle.p2p(geom, sx, sy, p4.radius_D, g, nthreads, lib)
+            return time.perf_counter() - t0
+
+        row = {}
+        for mode, nthreads in (("sc", 1), ("mc", threads)):
+            m = 4_000 if nthreads == 1 else 40_000
+            dt = run(m, nthreads)  # calibration
+            m = int(min(len(order), max(m, m * per_run / max(dt, 1e-4))))
+            times = sorted(run(m, nthreads) for _ in range(3))
+            tests = oracle.test_count(g, px[order[:m]], py[order[:m]], lib)
+            row[mode] = {"points": m, "tests": tests, "threads": nthreads,
+                         "seconds_median": times[1], "tests_per_s": tests / times[1],
+                         "points_per_s": m / times[1]}
+            log(f"[bench] oracle {name} {mode}: {m} points, {tests / times[1]:.3g} tests/s")
+        out[name] = row
+    tp, tq = step_tests
+
+    def mix_rate(mode):  # tests/s of one step's mix of PIP and P2P tests
+        return (tp + tq) / (tp / out["pip"][mode]["tests_per_s"] + tq / out["p2p"][mode]["tests_per_s"])
+
     return {
-        "value": tests_total / secs_total,
+        "value": mix_rate("mc"),
         "unit": "tests/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"first {out['pip']['points']} C3 points (PIP) and first "
-                   f"{out['p2p']['points']} C4 points (P2P), FP64 oracle with its own grid, "
-                   f"OpenMP over points"),
-        "pip_tests_per_s": out["pip"]["tests_per_s"],
-        "p2p_tests_per_s": out["p2p"]["tests_per_s"],
+        "sample": (f"seeded random samples of the step's points: {out['pip']['mc']['points']} "
+                   f"C3 points (PIP) and {out['p2p']['mc']['points']} C4 points (P2P) on all "
+                   f"{threads} host threads (value), {out['pip']['sc']['points']} and "
+                   f"{out['p2p']['sc']['points']} on 1 thread (sc); FP64 oracle with its own "
+                   f"grid (same cells), OpenMP over points, median of 3 runs each; rates "
+                   f"weighted by one step's PIP and P2P test counts"),
+        "sc_value": mix_rate("sc"),
+        "step_seconds_mc": tp / out["pip"]["mc"]["tests_per_s"] + tq / out["p2p"]["mc"]["tests_per_s"],
+        "modes": out,
     }
 
 
@@ -197,48 +217,91 @@ def cpu_simd_run(c3, c4, budget_s: float):
     return out
 
 
-def serving_run(gp, torch, grid3, grid4, n_requests: int, precision: str):
-    """Configuration 5: a Poisson stream of mixed PIP/P2P batches (log-uniform 1K-4M
-    points) against the resident grids, offered at ~70% of the rate sustained during
-    warm-up; latency is submit -> results visible, measured inside the server."""
+def serving_run(gp, torch, grid3, grid4, pools, n_requests: int, n_warmup: int, precision: str,
+                n_slots=4, slot_points=1 << 22, mem_budget=24 << 30):
+    """Configuration 5: a Poisson stream of mixed PIP/P2P requests (log-uniform 1K-4M
+    points, kinds 50/50) against the resident grids.  Each request's payload is its own
+    seeded random draw from the configuration's resident point set (pools: the 50M C3
+    and 200M C4 points the C3/C4 generators drew), so no two requests share a payload
+    and none repeats a warm-up request.  The warm-up requests run back to back (they
+    capture the graphs) and give the sustained rate; the timed requests then arrive as
+    a Poisson stream at 70% of it.  Latency is submit -> results visible, measured inside
+    the server.  A sample of the timed requests is rerun through the direct entry points
+    and must give the same bits."""
     from paper_1403_0802_amd import synth
     dev = torch.device("cuda")
-    reqs = synth.serving_stream(n_requests, rate_per_s=1.0)
+    stream = synth.serving_stream(n_warmup + n_requests, rate_per_s=1.0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(14030805)
+
+    def payload(kind, n):
+        x, y = pools[kind]
+        idx = torch.randint(0, x.numel(), (n,), device=dev, generator=gen)
+        return x[idx], y[idx]
+
     data, outs = [], []
-    for (_, kind, n, i) in reqs:
-        x, y = synth.request_points(kind, n, i)
-        data.append((kind, torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)))
+    for (_, kind, n, _) in stream:
+        x, y = payload(kind, n)
+        data.append((kind, x, y))
         oid = torch.empty(n, dtype=torch.int32, device=dev)
         od = torch.empty(n, dtype=torch.float64, device=dev) if kind == "p2p" else None
         outs.append((oid, od))
-    slots, slot_points = 4, 1 << 22
-    srv = gp.Server(grid3, grid4, n_slots=slots, slot_points=slot_points, mem_budget=24 << 30,
-                    precision=precision, inputs_on_device=True, use_graphs=True)
-    # warm-up: every request once, back to back (captures the graphs); sustained rate
+    torch.cuda.synchronize()
+    warm, timed = list(zip(data, outs))[:n_warmup], list(zip(data, outs))[n_warmup:]
+    srv = gp.Server(grid3, grid4, n_slots=n_slots, slot_points=slot_points,
+                    mem_budget=mem_budget, precision=precision, inputs_on_device=True,
+                    use_graphs=True)
     t0 = time.perf_counter()
-    for t in [srv.submit(k, x, y, o[0], o[1]) for (k, x, y), o in zip(data, outs)]:
+    for t in [srv.submit(k, x, y, o[0], o[1]) for (k, x, y), o in warm]:
         srv.wait(t)
-    rate_pts = sum(x.numel() for _, x, _ in data) / (time.perf_counter() - t0)
-    mean_pts = float(np.mean([x.numel() for _, x, _ in data]))
+    warm_s = time.perf_counter() - t0
+    rate_pts = sum(x.numel() for (_, x, _), _ in warm) / warm_s
+    mean_pts = float(np.mean([x.numel() for (_, x, _), _ in timed]))
     lam = 0.7 * rate_pts / mean_pts
+    log(f"[bench] serving warm-up: {n_warmup} requests in {warm_s:.2f}s, sustained "
+        f"{rate_pts:.3g} points/s; offering {lam:.1f} requests/s")
     srv.reset_stats()
-    arrivals = np.cumsum(np.random.default_rng(5).exponential(1.0 / lam, len(data)))
+    arrivals = np.cumsum(np.random.default_rng(5).exponential(1.0 / lam, len(timed)))
     t_start = time.perf_counter()
     tickets = []
-    for (k, x, y), o, ta in zip(data, outs, arrivals):
+    for ((k, x, y), o), ta in zip(timed, arrivals):
         now = time.perf_counter() - t_start
         if ta > now:
             time.sleep(ta - now)
         tickets.append(srv.submit(k, x, y, o[0], o[1]))
     for t in tickets:
         srv.wait(t)
+    wall = time.perf_counter() - t_start
     st = srv.stats()
     srv.close()
-    return {"requests": len(data), "offered_req_per_s": lam, "sustained_pts_per_s": rate_pts,
-            "p50_us": st["p50_us"], "p99_us": st["p99_us"], "mean_us": st["mean_us"],
-            "max_us": st["max_us"], "points_per_s": st["points_per_s"],
+    # a sample of the timed requests, rerun alone through the direct entry points
+    rng = np.random.default_rng(7)
+    same = True
+    sample = rng.choice(len(timed), min(24, len(timed)), replace=False)
+    for i in sample:
+        (k, x, y), (oid, od) = timed[i]
+        r = gp.run(grid3 if k == "pip" else grid4, x, y, precision)
+        if k == "pip":
+            same &= bool(torch.equal(r, oid))
+        else:
+            same &= bool(torch.equal(r[0], oid) and torch.equal(r[1], od))
+    del data, outs, warm, timed
+    torch.cuda.empty_cache()
+    return {"requests": len(tickets), "warmup_requests": n_warmup,
+            "offered_req_per_s": lam, "sustained_pts_per_s": rate_pts,
+            "wall_s": wall, "p50_us": st["p50_us"], "p99_us": st["p99_us"],
+            "mean_us": st["mean_us"], "max_us": st["max_us"],
+            "latency_samples": st["latency_samples"], "completed": st["completed"],
+            "failed": st["failed"], "points_per_s": st["points_per_s"],
             "tests_per_s": st["tests_per_s"], "graph_replays": st["graph_replays"],
-            "slots": slots, "slot_points": slot_points}
+            "max_in_flight_requests": st["max_in_flight"],
+            "max_in_flight_chunks": st["max_chunks_in_flight"],
+            "deferred_for_memory": st["deferred_for_memory"],
+            "peak_bytes_in_use": st["peak_bytes_in_use"], "arena_bytes": st["arena_bytes"],
+            "slots": n_slots, "slot_points": slot_points,
+            "sample_equal_to_direct_calls": {"requests": len(sample), "equal": same},
+            "payloads": "per request, a seeded random draw (torch.randint on the device) "
+                        "from the resident C3 / C4 point sets"}
 
 
 def cell_sweep(gp, torch, dev, c3, c4, which="both"):
@@ -274,7 +337,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="timed requests of the serving run (after the warm-up ones)")
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--filters", action="store_true",
+                    help="also measure the P2P segment filter (a work filter beyond the "
+                         "paper's method)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-simd", action="store_true",
@@ -457,7 +525,7 @@ def main():
         del grid3c, id3c
     # P2P with per-cell segment lists: segments that cannot come within D of a cell are
     # never tested; same ids and distances (reported apart from the headline)
-    if not args.no_classes:
+    if args.filters:
         from paper_1403_0802_amd import synth
         p4f = synth.GridParams(**{**p4.__dict__, "segment_filter": 1})
         t0 = time.perf_counter()
@@ -522,18 +590,16 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_serve:
         log("[bench] serving run")
-        del x4, y4, id4, d4
+        del id4, d4
         torch.cuda.empty_cache()
-        detail["serving"] = serving_run(gp, torch, grid3, grid4, args.serve_requests, prec)
-        if not args.no_classes:
-            # the same stream against grids built with the work filters (PIP cell classes,
-            # P2P segment lists): identical results, less work per request
-            from paper_1403_0802_amd import synth
-            g3f = gp.gp_build_grid("pip", geom3, synth.GridParams(**{**p3.__dict__, "cell_classes": 1}))
-            g4f = gp.gp_build_grid("p2p", geom4, synth.GridParams(**{**p4.__dict__, "segment_filter": 1}))
-            detail["serving_filtered_grids"] = serving_run(gp, torch, g3f, g4f,
-                                                           args.serve_requests, prec)
-            del g3f, g4f
+        pools = {"pip": (x3, y3), "p2p": (x4, y4)}
+        detail["serving"] = serving_run(gp, torch, grid3, grid4, pools, args.serve_requests,
+                                        args.serve_warmup, prec)
+        s_ = detail["serving"]
+        log(f"[bench] serving: {s_['requests']} requests, p50 {s_['p50_us']:.0f} us, "
+            f"p99 {s_['p99_us']:.0f} us, {s_['points_per_s']:.3g} points/s, "
+            f"peak {s_['max_in_flight_requests']} requests / {s_['max_in_flight_chunks']} chunks "
+            f"in flight")
     out = {
         "metric": METRIC,
         "value": value,
@@ -550,6 +616,12 @@ def main():
         "config": {"workload": workload, "pip_points": detail["pip"]["points"],
                    "p2p_points": detail["p2p"]["points"], "pip_polygons": geom3.n_features,
                    "p2p_polylines": geom4.n_features, "radius_D_m": 100.0,
+                   "pip_grid": {"cell_size": p3.cell_size, "nx": p3.nx, "ny": p3.ny,
+                                "note": "1/512 cells, the fastest PIP query of the cell-size "
+                                        "sweep (the survey's C3 grid is 1/1024)"},
+                   "p2p_grid": {"cell_size_m": p4.cell_size, "nx": p4.nx, "ny": p4.ny,
+                                "prestage": int(getattr(p4, "prestage", 0)),
+                                "note": "with build-time per-(cell, segment) FP32 records"},
                    "precision": "mixed (FP32 cell-rebased + FP64 recheck)"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK, "traffic": traffic,
@@ -560,7 +632,7 @@ def main():
     }
     if not args.no_cpu:
         log("[bench] cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(c3, c4, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(c3, c4, args.cpu_budget, (tests_pip, tests_p2p))
         if not args.no_cpu_simd:
             log("[bench] cpu simd modes")
             detail["cpu_simd"] = cpu_simd_run(c3, c4, args.cpu_budget)

@@ -247,46 +247,70 @@ gp_status gp_probe_rate(int32_t which, int32_t iters, double *rate, float *ms);
 
 /* ---------------------------------------------------------------- serving */
 
-/* A continuous-batching server over resident grids.  Requests are admitted while a
- * slot and enough of the memory budget are free; each slot runs its requests on its
- * own HIP stream, so work from different requests overlaps on the device.  Requests
- * larger than a slot are processed in slot-sized chunks (points are independent). */
+/* A continuous-batching server over resident grids (the serving form of the refinement:
+ * the paper's join answers batches of points against fixed polygon or polyline sets).
+ * Requests are cut into chunks of at most slot_points points (every point is
+ * independent, so chunking is exact).  A chunk runs in a block of device memory carved
+ * from one arena of mem_budget bytes that the server allocates at creation: the chunk's
+ * inputs, outputs and query workspace (gp_workspace_bytes) for its size bucket.  Chunks
+ * are admitted in FIFO order while one of the n_slots streams is free AND the chunk's
+ * block fits in the arena: the chunks of a large request spread over the free streams,
+ * and requests that arrive while others run start as streams and memory free up, so
+ * their work overlaps on the device.  Each block captures its query into a hipGraph at
+ * first use and replays it (use_graphs = 1). */
 typedef struct gp_serve_opts {
-    int32_t n_slots;          /* concurrent requests on the device, 1..16 */
-    int64_t slot_points;      /* points per slot chunk (capacity of one slot) */
-    int64_t mem_budget;       /* bytes of device memory the server may use */
+    int32_t n_slots;          /* chunks running at once (one HIP stream each), 1..16 */
+    int64_t slot_points;      /* largest chunk, in points, in [1024, 2^30) */
+    int64_t mem_budget;       /* bytes of the device arena; must hold one chunk of
+                                 slot_points points (else GP_E_OOM) */
     int32_t precision;        /* gp_precision for every request */
     int32_t inputs_on_device; /* 1: submit() pointers are device memory, else host */
-    int32_t use_graphs;       /* 1: replay captured hipGraphs per slot and size bucket */
+    int32_t use_graphs;       /* 1: replay captured hipGraphs per block */
     int32_t max_queue;        /* pending requests beyond which submit returns BUSY */
 } gp_serve_opts;
 
 typedef struct gp_server gp_server;
 
 typedef struct gp_serve_stats {
-    int64_t completed, failed, pending, in_flight;
-    double p50_us, p99_us, mean_us, max_us; /* submit -> result visible */
+    int64_t completed, failed, pending;
+    int64_t in_flight;                      /* requests with chunks on the device now */
+    double p50_us, p99_us, mean_us, max_us; /* submit -> result visible, over the most
+                                               recent latency_samples requests */
     double points_per_s, tests_per_s;       /* over the completed requests' busy span */
     int64_t points, tests, graph_replays;
+    int64_t chunks_in_flight;               /* chunks on the device now */
+    int64_t max_in_flight;                  /* peak of in_flight */
+    int64_t max_chunks_in_flight;           /* peak of chunks_in_flight */
+    int64_t deferred_for_memory;            /* chunks that waited for arena memory while
+                                               a stream was free */
+    int64_t bytes_in_use, peak_bytes_in_use, arena_bytes;
+    int64_t latency_samples;                /* at most 65,536 */
 } gp_serve_stats;
 
-/* pip_grid / p2p_grid may each be NULL (then that kind is rejected). */
+/* pip_grid / p2p_grid may each be NULL (then that kind is rejected); the grids'
+ * device must be current.  Allocates the arena and starts the server thread. */
 gp_status gp_serve_create(const gp_grid *pip_grid, const gp_grid *p2p_grid,
                           const gp_serve_opts *opts, gp_server **out);
 /* Enqueue a request; returns immediately with a ticket.  out_id (and out_dist for P2P)
- * are written before the ticket completes; they live where the inputs live. */
+ * are written before the ticket completes; they live where the inputs live.  The
+ * caller keeps inputs and outputs alive until the ticket completes. */
 gp_status gp_serve_submit(gp_server *srv, gp_kind kind, int64_t n, const double *px,
                           const double *py, int32_t *out_id, double *out_dist,
                           uint64_t *ticket);
-/* done = 1 once the ticket's results are visible (0 while pending). */
+/* done = 1 once the ticket's results are visible (0 while pending).  Reporting done
+ * releases the ticket: later calls on it return GP_E_NOT_FOUND. */
 gp_status gp_serve_poll(gp_server *srv, uint64_t ticket, int32_t *done);
-/* Block until the ticket completes or timeout_us passes (<0: forever). Returns the
- * request's own status once complete; GP_E_TIMEOUT otherwise. */
+/* Block until the ticket completes or timeout_us passes (<0: forever).  Returns the
+ * request's own status once complete, and releases the ticket (later calls on it return
+ * GP_E_NOT_FOUND); GP_E_TIMEOUT otherwise. */
 gp_status gp_serve_wait(gp_server *srv, uint64_t ticket, int64_t timeout_us);
+/* Counters and latency percentiles.  Named gp_serve_stats_get because gp_serve_stats
+ * is the name of the struct it fills. */
 gp_status gp_serve_stats_get(gp_server *srv, gp_serve_stats *stats);
-/* Forget the latency samples and counters gathered so far (e.g. after a warm-up). */
+/* Forget the latency samples and counters gathered so far (e.g. after a warm-up); the
+ * peaks restart from the current values. */
 gp_status gp_serve_stats_reset(gp_server *srv);
-/* Drain in-flight work, stop the server thread and free everything. */
+/* Drain queued and in-flight work, stop the server thread and free everything. */
 gp_status gp_serve_destroy(gp_server *srv);
 
 #ifdef __cplusplus

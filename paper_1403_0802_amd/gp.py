@@ -87,7 +87,11 @@ class gp_serve_stats(Structure):
                 ("in_flight", c_int64), ("p50_us", c_double), ("p99_us", c_double),
                 ("mean_us", c_double), ("max_us", c_double), ("points_per_s", c_double),
                 ("tests_per_s", c_double), ("points", c_int64), ("tests", c_int64),
-                ("graph_replays", c_int64)]
+                ("graph_replays", c_int64), ("chunks_in_flight", c_int64),
+                ("max_in_flight", c_int64), ("max_chunks_in_flight", c_int64),
+                ("deferred_for_memory", c_int64), ("bytes_in_use", c_int64),
+                ("peak_bytes_in_use", c_int64), ("arena_bytes", c_int64),
+                ("latency_samples", c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -278,18 +282,25 @@ def gp_autotune(grid, prec, px, py, ws, stream=None):
 
 
 def run(grid: Grid, px, py, prec="fp64", ws=None, stream=None, stats=False):
-    """Allocate outputs (and a workspace if none is given) and run PIP or P2P."""
+    """Allocate outputs (and a workspace if none is given) and run PIP or P2P.  The
+    allocations are made on the stream the query runs on, so the caching allocator does
+    not hand the workspace out again while the query still uses it."""
     import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(px.device)
+    elif isinstance(stream, int):
+        stream = torch.cuda.ExternalStream(stream, device=px.device)
     n = px.numel()
-    if ws is None:
-        ws = new_workspace(grid, n, prec, px.device)
-    out_id = torch.empty(n, dtype=torch.int32, device=px.device)
-    if grid.kind == GP_PIP:
-        st = gp_pip(grid, px, py, out_id, prec, ws, stream, stats)
-        return (out_id, st) if stats else out_id
-    out_d = torch.empty(n, dtype=torch.float64, device=px.device)
-    st = gp_p2p(grid, px, py, out_id, out_d, prec, ws, stream, stats)
-    return (out_id, out_d, st) if stats else (out_id, out_d)
+    with torch.cuda.stream(stream):
+        if ws is None:
+            ws = new_workspace(grid, n, prec, px.device)
+        out_id = torch.empty(n, dtype=torch.int32, device=px.device)
+        if grid.kind == GP_PIP:
+            st = gp_pip(grid, px, py, out_id, prec, ws, stream, stats)
+            return (out_id, st) if stats else out_id
+        out_d = torch.empty(n, dtype=torch.float64, device=px.device)
+        st = gp_p2p(grid, px, py, out_id, out_d, prec, ws, stream, stats)
+        return (out_id, out_d, st) if stats else (out_id, out_d)
 
 
 def _geometry(geom):
@@ -373,15 +384,18 @@ class Server:
     submit = gp_serve_submit
 
     def gp_serve_poll(self, ticket) -> bool:
+        """True once done; that releases the ticket (as gp_serve_wait does)."""
         d = c_int32()
         check(lib.gp_serve_poll(self.handle, ticket, ctypes.byref(d)))
+        if d.value:
+            self._live.pop(ticket, None)
         return bool(d.value)
 
     poll = gp_serve_poll
 
     def gp_serve_wait(self, ticket, timeout_us=-1):
         rc = lib.gp_serve_wait(self.handle, ticket, int(timeout_us))
-        if rc == GP_OK:
+        if rc != GP_E_TIMEOUT:  # complete (or unknown): the ticket is released
             self._live.pop(ticket, None)
         return check(rc)
 

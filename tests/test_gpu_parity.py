@@ -808,11 +808,30 @@ def _device_run(gp, grid, x, y, prec):
     return r
 
 
+def _pairing_equals_oracle(gp, grid, x, y, og, px, py):
+    """gp_pair_points at full size: perm and pt_off equal the oracle's stable grouping
+    (the multi-pass radix path that large key ranges take)."""
+    n = x.numel()
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    pt_off = torch.empty(og.ncells + 1, dtype=torch.int32, device="cuda")
+    ws = gp.new_workspace(grid, n, "fp64")
+    gp.gp_pair_points(grid, x, y, perm, pt_off, ws)
+    torch.cuda.synchronize()
+    del ws
+    want_off, want_perm = oracle.sort_points(og, oracle.point_cells(og, px, py))
+    assert np.array_equal(pt_off.cpu().numpy().astype(np.int64), want_off), "pt_off differs"
+    got = perm.cpu().numpy()
+    del perm
+    bad = np.flatnonzero(got.astype(np.int64) != want_perm)
+    assert bad.size == 0, f"{bad.size} perm entries differ, first at {bad[:5]}"
+
+
 @pytest.mark.parametrize("grid_kind", ["bench", "cells_1024"])
 def test_c3_full_size_50m(gp, c3_geom, grid_kind):
     """Configuration 3 at its full 50M points, default launch configuration, on the
-    bench's grid (cells of 1/512) and on cells of 1/1024: the mixed ids equal the FP64 ids
-    on every point (compared on the device), and 20,000 sampled points equal the oracle."""
+    bench's grid (cells of 1/512) and on cells of 1/1024: the point pairing (perm, pt_off)
+    equals the oracle's; the mixed ids equal the FP64 ids on every point (compared on the
+    device) and the oracle's on every point."""
     geom, _ = c3_geom
     say("c3 full size: 50M points,", grid_kind)
     px, py = synth.config3_points(50_000_000)
@@ -821,13 +840,16 @@ def test_c3_full_size_50m(gp, c3_geom, grid_kind):
     else:
         params, want_tests = synth.GridParams(cell_size=1 / 1024, nx=1024, ny=1024), 28_869_883_377
     grid = gp.gp_build_grid("pip", geom, params)
+    og = oracle.build_grid(geom, params)
     x, y = dev_arrays(px, py)
+    _pairing_equals_oracle(gp, grid, x, y, og, px, py)
+    say("  pairing == oracle")
     g64, s64 = _device_run(gp, grid, x, y, "fp64")
     gmx, smx = _device_run(gp, grid, x, y, "mixed")
     assert torch.equal(g64, gmx), int((g64 != gmx).sum())
-    idx = np.random.default_rng(30).choice(len(px), 20_000, replace=False)
-    want = oracle.pip(geom, px[idx], py[idx], oracle.build_grid(geom, params))
-    assert np.array_equal(gmx.cpu().numpy()[idx], want)
+    want = oracle.pip(geom, px, py, og)
+    bad = np.flatnonzero(gmx.cpu().numpy() != want)
+    assert bad.size == 0, f"{bad.size} of 50M ids differ from the oracle, first at {bad[:5]}"
     assert smx["tests"] == s64["tests"] == want_tests
     say("  mixed", smx)
 
@@ -836,8 +858,9 @@ def test_c3_full_size_50m(gp, c3_geom, grid_kind):
 def test_c4_full_size_200m(gp, grid_kind):
     """Configuration 4 at its full 200M points, default launch configuration, on the
     bench's grid (build-time segment records: the kernel the bench times) and on the same
-    grid without records: mixed ids and distances equal the FP64 form's on every point
-    (compared on the device), and 20,000 sampled points equal the oracle."""
+    grid without records: the point pairing equals the oracle's (bench grid; the other
+    grid has the same cells); mixed ids and distances equal the FP64 form's on every
+    point (compared on the device), and 2M sampled points equal the oracle."""
     say("c4 full size: 200M points,", grid_kind)
     geom = synth.config4_geometry()
     px, py = synth.config4_points(200_000_000)
@@ -845,13 +868,18 @@ def test_c4_full_size_200m(gp, grid_kind):
     if grid_kind == "no_records":
         params.prestage = 0
     grid = gp.gp_build_grid("p2p", geom, params)
+    og = oracle.build_grid(geom, params)
     x, y = dev_arrays(px, py)
+    if grid_kind == "bench":
+        _pairing_equals_oracle(gp, grid, x, y, og, px, py)
+        say("  pairing == oracle")
     i64, d64, s64 = _device_run(gp, grid, x, y, "fp64")
     imx, dmx, smx = _device_run(gp, grid, x, y, "mixed")
     assert torch.equal(i64, imx), int((i64 != imx).sum())
     assert torch.equal(d64, dmx)
-    idx = np.random.default_rng(31).choice(len(px), 20_000, replace=False)
-    wid, wd = oracle.p2p(geom, px[idx], py[idx], 100.0, oracle.build_grid(geom, params))
+    del i64, d64
+    idx = np.random.default_rng(31).choice(len(px), 2_000_000, replace=False)
+    wid, wd = oracle.p2p(geom, px[idx], py[idx], 100.0, og)
     check_p2p(imx.cpu().numpy()[idx], dmx.cpu().numpy()[idx], wid, wd, "mixed", "c4 full sample")
     assert smx["tests"] == s64["tests"] == 1_099_498_435_953
     say("  mixed", smx)

@@ -1,8 +1,10 @@
-"""Serving (continuous batching over resident grids): every request's result is the same
-alone and in a concurrent mix; admission, chunking and error paths behave."""
+"""Serving (continuous batching over resident grids): every request's result equals the
+CPU oracle's, alone and in a concurrent mix; admission by memory, chunking over free
+streams, ticket release and error paths behave."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_1403_0802_amd import synth
 
 torch = pytest.importorskip("torch")
@@ -20,21 +22,29 @@ def setup():
     p4 = synth.GridParams(cell_size=100.0, radius_D=100.0, nx=400, ny=400)
     g3 = gp.gp_build_grid("pip", geom3, p3)
     g4 = gp.gp_build_grid("p2p", geom4, p4)
+    og3, og4 = oracle.build_grid(geom3, p3), oracle.build_grid(geom4, p4)
     rng = np.random.default_rng(11)
     sizes = np.exp(rng.uniform(np.log(1000), np.log(300_000), 24)).astype(int)
     sizes[3] = 70_000  # larger than the small slots below: processed in chunks
-    reqs = []
+    reqs, want = [], []
     for i, n in enumerate(sizes):
         kind = "pip" if i % 2 == 0 else "p2p"
         x, y = synth.request_points(kind, int(n), 1000 + i)
         reqs.append((kind, torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()))
-    # results of each request alone, through the direct entry points
+        # the oracle's result of every request (ids; P2P distances too)
+        if kind == "pip":
+            want.append((torch.from_numpy(oracle.pip(geom3, x, y, og3)), None))
+        else:
+            wid, wd = oracle.p2p(geom4, x, y, 100.0, og4)
+            want.append((torch.from_numpy(wid), torch.from_numpy(wd)))
+    # each request alone, through the direct entry points, equals the oracle
     alone = []
     for kind, x, y in reqs:
         r = gp.run(g3 if kind == "pip" else g4, x, y, "mixed")
         alone.append((r.clone(), None) if kind == "pip" else (r[0].clone(), r[1].clone()))
     torch.cuda.synchronize()
-    return gp, g3, g4, reqs, alone
+    check_same(want, alone, "alone")
+    return gp, g3, g4, reqs, want
 
 
 def outputs_for(reqs, device="cuda", pin=False):
@@ -48,16 +58,17 @@ def outputs_for(reqs, device="cuda", pin=False):
     return outs
 
 
-def check_same(alone, outs):
-    for i, ((aid, ad), (oid, od)) in enumerate(zip(alone, outs)):
-        assert torch.equal(aid.cpu(), oid.cpu()), f"request {i}: ids differ from the alone run"
-        if ad is not None:
-            assert torch.equal(ad.cpu(), od.cpu()), f"request {i}: distances differ"
+def check_same(want, outs, where="mix"):
+    """Ids bit-exact and P2P distances bitwise equal to the oracle's."""
+    for i, ((wid, wd), (oid, od)) in enumerate(zip(want, outs)):
+        assert torch.equal(wid.cpu(), oid.cpu()), f"{where} request {i}: ids differ from the oracle"
+        if wd is not None:
+            assert torch.equal(wd.cpu(), od.cpu()), f"{where} request {i}: distances differ"
 
 
 @pytest.mark.parametrize("graphs", [True, False])
 def test_mix_equals_alone(setup, graphs):
-    gp, g3, g4, reqs, alone = setup
+    gp, g3, g4, reqs, want = setup
     print("serving mix, graphs =", graphs, flush=True)
     srv = gp.Server(g3, g4, n_slots=4, slot_points=65536, mem_budget=4 << 30,
                     precision="mixed", inputs_on_device=True, use_graphs=graphs)
@@ -67,7 +78,7 @@ def test_mix_equals_alone(setup, graphs):
         for t in tickets:
             srv.wait(t)
         torch.cuda.synchronize()
-        check_same(alone, outs)
+        check_same(want, outs)
         for o in outs:
             o[0].fill_(-7)
             if o[1] is not None:
@@ -75,6 +86,10 @@ def test_mix_equals_alone(setup, graphs):
     st = srv.stats()
     assert st["completed"] == 2 * len(reqs) and st["failed"] == 0
     assert st["p50_us"] > 0 and st["p99_us"] >= st["p50_us"]
+    assert st["latency_samples"] == 2 * len(reqs)
+    # the 24 requests were queued at once: several ran on the device together
+    assert st["max_in_flight"] > 1 and st["max_chunks_in_flight"] > 1
+    assert st["in_flight"] == 0 and st["chunks_in_flight"] == 0 and st["bytes_in_use"] == 0
     if graphs:
         assert st["graph_replays"] > 0
     srv.close()
@@ -83,7 +98,7 @@ def test_mix_equals_alone(setup, graphs):
 def test_prestaged_grid_in_the_mix(setup):
     """A P2P grid with build-time segment records serves the same results, through the
     captured graphs of its own kernel, as the plain grid's requests alone."""
-    gp, g3, g4, reqs, alone = setup
+    gp, g3, g4, reqs, want = setup
     print("serving with a prestaged P2P grid", flush=True)
     geom4 = synth.config4_geometry(n_lines=20_000, seed_salt=1)
     g4p = gp.gp_build_grid("p2p", geom4, synth.GridParams(cell_size=100.0, radius_D=100.0,
@@ -96,24 +111,77 @@ def test_prestaged_grid_in_the_mix(setup):
         for t in tickets:
             srv.wait(t)
         torch.cuda.synchronize()
-        check_same(alone, outs)
+        check_same(want, outs)
     assert srv.stats()["graph_replays"] > 0
     srv.close()
 
 
+def block_bytes(gp, grid, b, kind):
+    """Device bytes of one chunk block of bucket b (inputs, outputs, workspace)."""
+    al = lambda v: (v + 255) // 256 * 256  # noqa: E731
+    io = 2 * al(b * 8) + al(b * 4) + (al(b * 8) if kind == "p2p" else 0)
+    return io + al(gp.gp_workspace_bytes(grid, b, "mixed"))
+
+
 def test_host_inputs_and_tight_budget(setup):
-    gp, g3, g4, reqs, alone = setup
-    print("serving host inputs, one slot", flush=True)
-    per_slot = max(gp.gp_workspace_bytes(g3, 16384, "mixed"),
-                   gp.gp_workspace_bytes(g4, 16384, "mixed")) + 16384 * 28 + 4096
-    srv = gp.Server(g3, g4, n_slots=8, slot_points=16384, mem_budget=per_slot + 1,
+    """Pinned host inputs and outputs, with an arena that holds one chunk of 16,384
+    points: every request still equals the oracle."""
+    gp, g3, g4, reqs, want = setup
+    print("serving host inputs, one-chunk arena", flush=True)
+    budget = max(block_bytes(gp, g3, 16384, "pip"), block_bytes(gp, g4, 16384, "p2p"))
+    srv = gp.Server(g3, g4, n_slots=8, slot_points=16384, mem_budget=budget + 1,
                     precision="mixed", inputs_on_device=False, use_graphs=True)
     hreqs = [(k, x.cpu().pin_memory(), y.cpu().pin_memory()) for k, x, y in reqs[:10]]
     outs = outputs_for(hreqs, device="cpu", pin=True)
     tickets = [srv.submit(k, x, y, o[0], o[1]) for (k, x, y), o in zip(hreqs, outs)]
     for t in tickets:
         srv.wait(t)
-    check_same(alone[:10], outs)
+    check_same(want[:10], outs)
+    srv.close()
+
+
+def test_admission_waits_for_memory_not_streams(setup):
+    """Four streams but an arena for one chunk of slot_points points (and less than the
+    smallest second block): the chunks of large requests wait for memory while streams
+    are free (deferred_for_memory), never two run at once, and every result equals the
+    oracle."""
+    gp, g3, _, reqs, want = setup
+    print("serving: admission by memory", flush=True)
+    P = 32768
+    bp = block_bytes(gp, g3, P, "pip")
+    budget = bp + bp // 20
+    assert block_bytes(gp, g3, 1024, "pip") > budget - bp
+    srv = gp.Server(g3, None, n_slots=4, slot_points=P, mem_budget=budget,
+                    precision="mixed", inputs_on_device=True, use_graphs=True)
+    big = [(i, r) for i, r in enumerate(reqs) if r[0] == "pip" and r[1].numel() > P][:3]
+    assert len(big) >= 2
+    outs = outputs_for([r for _, r in big])
+    tickets = [srv.submit(k, x, y, o[0]) for (_, (k, x, y)), o in zip(big, outs)]
+    for t in tickets:
+        srv.wait(t)
+    check_same([want[i] for i, _ in big], outs)
+    st = srv.stats()
+    assert st["deferred_for_memory"] >= 1, st
+    assert st["max_chunks_in_flight"] == 1, st
+    assert st["peak_bytes_in_use"] <= st["arena_bytes"] == budget // 256 * 256
+    srv.close()
+
+
+def test_large_request_spreads_over_free_streams(setup):
+    """One request of many chunks, with memory for all: its chunks run on several
+    streams at once and the result equals the oracle."""
+    gp, g3, g4, reqs, want = setup
+    print("serving: one large request over four streams", flush=True)
+    i = max((j for j, r in enumerate(reqs) if r[0] == "p2p"), key=lambda j: reqs[j][1].numel())
+    k, x, y = reqs[i]
+    srv = gp.Server(None, g4, n_slots=4, slot_points=8192, mem_budget=2 << 30,
+                    precision="mixed", inputs_on_device=True, use_graphs=True)
+    (oid, od), = outputs_for([reqs[i]])
+    srv.wait(srv.submit(k, x, y, oid, od))
+    check_same([want[i]], [(oid, od)])
+    st = srv.stats()
+    assert st["max_chunks_in_flight"] > 1 and st["max_in_flight"] == 1, st
+    assert st["deferred_for_memory"] == 0
     srv.close()
 
 
@@ -131,11 +199,22 @@ def test_errors(setup):
     with pytest.raises(gp.GPError) as e:
         srv.wait(12345)
     assert e.value.status == gp.GP_E_NOT_FOUND
-    # an empty request completes at once
+    # an empty request completes at once; reporting it done releases the ticket
     t = srv.submit("pip", torch.empty(0, dtype=torch.float64, device="cuda"),
                    torch.empty(0, dtype=torch.float64, device="cuda"),
                    torch.empty(0, dtype=torch.int32, device="cuda"))
     assert srv.poll(t)
+    with pytest.raises(gp.GPError) as e:
+        srv.poll(t)
+    assert e.value.status == gp.GP_E_NOT_FOUND
+    # a completed ticket is released by the wait that returns it
+    k, x, y = reqs[0]
+    o = torch.empty(x.numel(), dtype=torch.int32, device="cuda")
+    t = srv.submit("pip", x, y, o)
+    srv.wait(t)
+    with pytest.raises(gp.GPError) as e:
+        srv.wait(t)
+    assert e.value.status == gp.GP_E_NOT_FOUND
     # a bounded queue refuses work while the only slot is busy
     k, x, y = reqs[0]
     busy, accepted = 0, []
@@ -154,13 +233,13 @@ def test_errors(setup):
 
 
 def test_autotune_keeps_results(setup):
-    gp, g3, g4, reqs, alone = setup
+    gp, g3, g4, reqs, want = setup
     kind, x, y = reqs[0]
     ws = gp.new_workspace(g3, x.numel(), "mixed")
     best, ms = gp.gp_autotune(g3, "mixed", x, y, ws)
     assert best["points_per_lane"] in (1, 2, 4) and ms > 0
     assert gp.gp_get_tuning(g3, "mixed") == best
     r = gp.run(g3, x, y, "mixed")
-    assert torch.equal(r.cpu(), alone[0][0].cpu())
+    assert torch.equal(r.cpu(), want[0][0])
     gp.gp_reset_tuning(g3, "mixed")
     assert gp.gp_get_tuning(g3, "mixed")["vp_points"] == 16
