@@ -207,6 +207,20 @@ gp_status gp_p2p(const gp_grid *grid, int64_t n, const double *px, const double 
                  int32_t *out_id, double *out_dist, gp_precision prec, void *ws,
                  size_t ws_bytes, void *hip_stream, gp_stats *stats);
 
+/* For callers that cannot allocate device memory (code under hipGraph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): gp_pip (kind GP_PIP, out_dist
+ * ignored) or gp_p2p (kind GP_P2P) with the workspace taken from a buffer the library
+ * holds on each GPU (GP_NOALLOC_SCRATCH_BYTES, kept until the process ends) instead of
+ * a caller workspace.  Allocates nothing; inputs and outputs are the caller's device
+ * pointers, as for gp_pip / gp_p2p, with the same results.  GP_E_CAPACITY when the
+ * workspace for n points (gp_workspace_bytes) exceeds the buffer.  Every call on one GPU
+ * shares that GPU's buffer: calls that overlap on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller.  Asynchronous on hip_stream. */
+#define GP_NOALLOC_SCRATCH_BYTES (64ull << 20)
+gp_status gp_query_noalloc(const gp_grid *grid, gp_kind kind, int64_t n, const double *px,
+                           const double *py, int32_t *out_id, double *out_dist,
+                           gp_precision prec, void *hip_stream);
+
 /* Kernel configuration of a grid for one precision form.  gp_set_tuning with a NULL
  * tuning restores the library default. */
 gp_status gp_set_tuning(gp_grid *grid, gp_precision prec, const gp_tuning *tuning);

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgp.so")
-SOURCES = ["gp_kernels.hip", "gp_serve.hip", "gp_probe.hip", "gp_api.cpp"]
+SOURCES = ["gp_kernels.hip", "gp_serve.hip", "gp_probe.hip", "gp_noalloc.hip", "gp_api.cpp"]
 ARCH = os.environ.get("GP_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -34,6 +34,7 @@ GP_FP64 = 0
 GP_MIXED = 1
 
 PRECISIONS = {"fp64": GP_FP64, "mixed": GP_MIXED}
+GP_NOALLOC_SCRATCH_BYTES = 64 << 20  # the workspace gp_query_noalloc holds per GPU
 KINDS = {"pip": GP_PIP, "p2p": GP_P2P}
 
 
@@ -111,6 +112,7 @@ _SIGS = {
                c_int32),
     "gp_p2p": ([_P, c_int64, _P, _P, _P, _P, c_int32, _P, ctypes.c_size_t, _P,
                 POINTER(gp_stats)], c_int32),
+    "gp_query_noalloc": ([_P, c_int32, c_int64, _P, _P, _P, _P, c_int32, _P], c_int32),
     "gp_set_tuning": ([_P, c_int32, POINTER(gp_tuning)], c_int32),
     "gp_get_tuning": ([_P, c_int32, POINTER(gp_tuning)], c_int32),
     "gp_autotune": ([_P, c_int32, c_int64, _P, _P, _P, ctypes.c_size_t, _P, POINTER(gp_tuning),
