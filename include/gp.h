@@ -111,11 +111,16 @@ typedef struct gp_geometry {
  * D from the whole cell can neither be a point's nearest segment within range nor bring
  * a polyline into range), with the same results; tests and tests_avoided as above.  The
  * GP_FP64 form keeps testing every candidate segment.
- * p2p_prestage = 1 (P2P only; 0 otherwise; ignored with p2p_segment_filter) computes at
- * build time, for every cell, the cell-relative FP32 records of all its candidate
- * segments and the cell's error bounds, which GP_MIXED queries then read instead of
- * computing them per work item: 20 bytes per (cell, candidate segment), reported in
- * gp_grid_info.device_bytes.  Same results. */
+ * prestage = 1 (0 otherwise) computes at build time, for every cell, the cell-relative
+ * FP32 records of the GP_MIXED form, which its queries then read instead of computing
+ * them per work item; same results.  P2P (ignored with p2p_segment_filter): the records
+ * of all the cell's candidate segments and the cell's error bounds, 20 bytes per (cell,
+ * candidate segment).  PIP: per (cell, candidate polygon) pair its edges' records in
+ * three classes -- edges whose FP32 crossing test equals the FP64 predicate for every
+ * point of the cell, edges right of the cell whose crossing reduces to the half-open
+ * straddle of the point's y (with a flag for a point level with an endpoint in FP32), and
+ * guarded edges near the cell (test plus error-band flag) -- 16 bytes per edge (32 per
+ * guarded edge).  Reported in gp_grid_info.device_bytes. */
 typedef struct gp_grid_params {
     double cell_size;
     double radius_D;
@@ -123,7 +128,7 @@ typedef struct gp_grid_params {
     int64_t nx, ny;
     int32_t pip_cell_classes;
     int32_t p2p_segment_filter;
-    int32_t p2p_prestage;
+    int32_t prestage;
 } gp_grid_params;
 
 typedef struct gp_grid gp_grid;

@@ -168,8 +168,8 @@ extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
     return set_error(GP_E_INVALID_ARG, "pip_cell_classes must be 0 or 1");
   if (params->p2p_segment_filter != 0 && params->p2p_segment_filter != 1)
     return set_error(GP_E_INVALID_ARG, "p2p_segment_filter must be 0 or 1");
-  if (params->p2p_prestage != 0 && params->p2p_prestage != 1)
-    return set_error(GP_E_INVALID_ARG, "p2p_prestage must be 0 or 1");
+  if (params->prestage != 0 && params->prestage != 1)
+    return set_error(GP_E_INVALID_ARG, "prestage must be 0 or 1");
   const bool derive = params->nx == 0 || params->ny == 0;
   if (!derive && (!std::isfinite(params->x0) || !std::isfinite(params->y0)))
     return set_error(GP_E_INVALID_ARG, "non-finite grid origin");
@@ -401,6 +401,48 @@ extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
     GP_TRY_HIP_G(launch_cell_edges(g->d_cand_off, g->d_cand_id, g->d_eoff, g->d_cand_class,
                                    ncells, g->d_cell_edges, s));
     GP_TRY_HIP_G(hipStreamSynchronize(s));
+    if (kind == GP_PIP && params->prestage && npairs > 0) {
+      // every (cell, candidate polygon) pair's edge records for the mixed test: classes
+      // counted on the device, slot offsets summed here in 64 bits, records emitted
+      const float hb = half_box(*g);
+      DevBuf d_cnt;
+      GP_TRY_HIP_G(d_cnt.alloc((size_t)npairs * sizeof(int2)));
+      GP_TRY_HIP_G(launch_pip_rec_count(skeys, g->d_cand_id, (int32_t)npairs, g->d_eoff,
+                                        g->d_edge64, g->d_k32, x0, y0, cs, g->nx, hb,
+                                        d_cnt.as<int2>(), s));
+      std::vector<int2> cnt(npairs), pc(npairs);
+      std::vector<int32_t> cid(npairs);
+      GP_TRY_HIP_G(hipMemcpyAsync(cnt.data(), d_cnt.p, (size_t)npairs * sizeof(int2),
+                                  hipMemcpyDeviceToHost, s));
+      GP_TRY_HIP_G(hipMemcpyAsync(cid.data(), g->d_cand_id, (size_t)npairs * 4,
+                                  hipMemcpyDeviceToHost, s));
+      GP_TRY_HIP_G(hipStreamSynchronize(s));
+      std::vector<int64_t> off((size_t)npairs + 1, 0);
+      for (size_t k = 0; k < npairs; ++k) {
+        const int32_t f = cid[k];
+        const int64_t ne = h.rvo[h.fro[f + 1]] - h.rvo[h.fro[f]];
+        const int32_t nb = cnt[k].x, ng = cnt[k].y, np = (int32_t)(ne - nb - ng);
+        pc[k] = make_int2(np, nb);
+        off[k + 1] = off[k] + ((np + nb + 1) & ~1) + 2 * (int64_t)ng;
+      }
+      g->nprec = off[npairs];
+      GP_TRY_HIP_G(hipMalloc(&g->d_prec_off, off.size() * 8));
+      GP_TRY_HIP_G(hipMalloc(&g->d_pcnt, (size_t)npairs * sizeof(int2)));
+      if (hipMalloc(&g->d_precs, (size_t)std::max<int64_t>(g->nprec, 1) * sizeof(float4)) !=
+          hipSuccess) {
+        g->d_precs = nullptr;
+        return fail(set_error(GP_E_OOM, "%lld PIP records (%lld bytes) do not fit",
+                              (long long)g->nprec, (long long)g->nprec * 16));
+      }
+      GP_TRY_HIP_G(hipMemcpyAsync(g->d_prec_off, off.data(), off.size() * 8,
+                                  hipMemcpyHostToDevice, s));
+      GP_TRY_HIP_G(hipMemcpyAsync(g->d_pcnt, pc.data(), (size_t)npairs * sizeof(int2),
+                                  hipMemcpyHostToDevice, s));
+      GP_TRY_HIP_G(launch_pip_rec_emit(skeys, g->d_cand_id, (int32_t)npairs, g->d_eoff,
+                                       g->d_edge64, g->d_k32, x0, y0, cs, g->nx, hb,
+                                       g->d_prec_off, g->d_pcnt, g->d_precs, s));
+      GP_TRY_HIP_G(hipStreamSynchronize(s));
+    }
   }
   if (kind == GP_P2P && params->p2p_segment_filter && nedges > 0) {
     // (cell, segment) pairs: every segment's box, expanded by D and padded like the MBBs,
@@ -450,7 +492,7 @@ extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
     GP_TRY_HIP_G(launch_cell_counts(g->d_cseg_off, ncells, g->d_cell_segs, s));
     GP_TRY_HIP_G(hipStreamSynchronize(s));
   }
-  if (kind == GP_P2P && params->p2p_prestage && !params->p2p_segment_filter && nedges > 0) {
+  if (kind == GP_P2P && params->prestage && !params->p2p_segment_filter && nedges > 0) {
     // every cell's segment records, in the order the refinement reads them, at offsets
     // from the prefix sum of the cells' candidate segment counts
     std::vector<int64_t> off((size_t)ncells + 1);
@@ -499,6 +541,9 @@ extern "C" void gp_grid_free(gp_grid *g) {
   (void)hipFree(g->d_recU);
   (void)hipFree(g->d_recV);
   (void)hipFree(g->d_cellE);
+  (void)hipFree(g->d_precs);
+  (void)hipFree(g->d_prec_off);
+  (void)hipFree(g->d_pcnt);
   delete g;
 }
 
@@ -511,6 +556,7 @@ static int64_t grid_device_bytes(const Grid &g) {
   if (g.d_cand_class) b += np + nc * 8;
   if (g.d_cseg_off) b += (nc + 1) * 4 + std::max<int64_t>(g.ncseg, 1) * 4 + ne * 4 + nc * 8;
   if (g.d_recU) b += (nc + 1) * 8 + std::max<int64_t>(g.nrec, 1) * 20 + nc * 8;
+  if (g.d_precs) b += (np + 1) * 8 + np * 8 + std::max<int64_t>(g.nprec, 1) * 16;
   return b;
 }
 
@@ -671,6 +717,10 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   a.recV = pre ? g->d_recV : nullptr;
   a.rec_off = pre ? g->d_rec_off : nullptr;
   a.cellE = pre ? g->d_cellE : nullptr;
+  const bool pip_pre = prec == GP_MIXED && g->d_precs != nullptr;
+  a.precs = pip_pre ? g->d_precs : nullptr;
+  a.prec_off = pip_pre ? g->d_prec_off : nullptr;
+  a.pcnt = pip_pre ? g->d_pcnt : nullptr;
   a.x0 = g->x0;
   a.y0 = g->y0;
   a.cs = g->cs;

@@ -48,6 +48,10 @@ struct RefineArgs {
   const int64_t *rec_off;    //   [ncells+1]
   const float2 *cellE;       //   [ncells] E over near segments, E over all
   const int2 *near;          // P2P: [npairs] near-segment range of each (cell, candidate)
+  const float4 *precs;       // PIP mixed, optional build-time records: per (cell, candidate)
+  const int64_t *prec_off;   //   pair its edges' records from prec_off[k] (float4 slots):
+  const int2 *pcnt;          //   pcnt[k].x plain, pcnt[k].y band, then from the next even
+                             //   slot the guarded ones (two slots each) up to prec_off[k+1]
   double x0, y0, cs;
   int32_t nx, ncells;
   double D, D2, D2_next;     // P2P: D, fl(D*D), the smallest double above fl(D*D)
@@ -99,6 +103,10 @@ struct Grid {
   float2 *d_cellE;
   int64_t nrec;
   float p2p_scale;        // see RefineArgs
+  float4 *d_precs;        // PIP build-time records (prestage), see RefineArgs
+  int64_t *d_prec_off;
+  int2 *d_pcnt;
+  int64_t nprec;
   gp_tuning tune[2];
   int num_cu;
 };
@@ -171,6 +179,17 @@ hipError_t launch_prestage(const int32_t *cand_off, const int32_t *cand_id, cons
                            double cs, int32_t nx, int32_t ncells, double D, float hb, float T,
                            float sc, const int64_t *rec_off, float4 *recU, float *recV,
                            float2 *cellE, hipStream_t s);
+// PIP build-time records: (band, guarded) counts of every (cell, candidate polygon) pair,
+// then the records at the per-pair slot offsets off[] with the (plain, band) counts pc[].
+hipError_t launch_pip_rec_count(const uint32_t *pair_cell, const int32_t *cand_id,
+                                int32_t npairs, const int32_t *eoff, const double4 *edge64,
+                                const float *k32, double x0, double y0, double cs, int32_t nx,
+                                float hb, int2 *cnt, hipStream_t s);
+hipError_t launch_pip_rec_emit(const uint32_t *pair_cell, const int32_t *cand_id,
+                               int32_t npairs, const int32_t *eoff, const double4 *edge64,
+                               const float *k32, double x0, double y0, double cs, int32_t nx,
+                               float hb, const int64_t *off, const int2 *pc, float4 *recs,
+                               hipStream_t s);
 hipError_t launch_seg_boxes(const double4 *seg64, int32_t nseg, double D, double pad,
                             double *box, hipStream_t s);
 hipError_t launch_seg2f(const int32_t *eoff, int32_t nf, int32_t *seg2f, hipStream_t s);

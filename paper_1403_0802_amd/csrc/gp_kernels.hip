@@ -1354,6 +1354,295 @@ __device__ void pipmix_item(const RefineArgs &a, const Item it, float4 *ldsA, fl
   }
 }
 
+// ------------------------------------------------------------------------- PIP, build-time records
+// With prestage the grid build classifies every edge of every (cell, candidate polygon)
+// pair once, for the mixed test of that cell (FP32 on coordinates rebased to the cell
+// centre, hb the bound on a point's rebased coordinates), and stores the records the
+// refinement reads:
+//  PIP_PLAIN   horizontal, wholly above or below the cell's y band, wholly left of the
+//              cell, or spanning the band strictly while right of it: the 4-instruction
+//              test (subtract, FMA, straddle and x compares) equals the FP64 predicate for
+//              every point of the cell.  Record (lo.x, lo.y, hi.y - lo.y, slope).
+//  PIP_BAND    right of the cell by more than 2G over the band, with an endpoint inside it:
+//              for every point of the cell the x part of the predicate holds in FP32 and
+//              in FP64, so the crossing is the half-open straddle lo.y <= p.y < hi.y.  With
+//              t = fl32(p.y - lo.y) and h = fl32(hi.y - lo.y) (rebased values), 0 < t < h
+//              implies the FP64 straddle and t < 0 or t > h rules it out (rounding is
+//              monotone); t = 0 or t = h is ambiguous and flags the (point, polygon) pair.
+//              Record (lo.y, bits(h) - 1, bits(h), 0): the open straddle is one unsigned
+//              compare of bits(t) - 1, the closed one of bits(t).
+//  PIP_GUARDED everything else: the full test and the error-band flag, two slots
+//              (lo.x, lo.y, hi.y, slope), (G, 0, 0, 0).
+enum { PIP_PLAIN = 0, PIP_BAND = 1, PIP_GUARDED = 2 };
+
+struct PipEdge {
+  int cls;
+  float4 rec;
+  float G;
+};
+
+__device__ __forceinline__ PipEdge pip_classify(const double4 r, float kk, double cx, double cy,
+                                                float hb) {
+  PipEdge o;
+  const float lx = (float)(r.x - cx), ly = (float)(r.y - cy), hy = (float)(r.w - cy);
+  const bool horiz = r.y == r.w;
+  const float h32 = hy - ly;
+  o.G = 0x1p-22f * (fabsf(kk) * (3.0f * hb + 3.0f * fabsf(ly)) + fabsf(lx) + 3.0f * hb);
+  const bool yout = (ly > hb) || (hy < -hb);
+  const bool ystrict = (ly < -hb) && (hy > hb + 0x1p-20f * h32);
+  const float ya = fmaxf(ly, -hb), yb = fminf(hy, hb);
+  const float xa = fmaf(ya - ly, kk, lx), xb = fmaf(yb - ly, kk, lx);
+  const bool xleft = fmaxf(xa, xb) < -hb - 2.0f * o.G;
+  const bool xright = fminf(xa, xb) > hb + 2.0f * o.G;
+  if (horiz || yout || xleft || (ystrict && xright)) {
+    o.cls = PIP_PLAIN;
+    o.rec = horiz ? make_float4(0.f, 3.0e38f, 0.f, 0.f) : make_float4(lx, ly, h32, kk);
+  } else if (xright) {
+    o.cls = PIP_BAND;
+    const uint32_t hbits = __float_as_uint(h32);
+    o.rec = make_float4(ly, __uint_as_float(hbits ? hbits - 1u : 0u), __uint_as_float(hbits),
+                        0.f);
+  } else {
+    o.cls = PIP_GUARDED;
+    o.rec = make_float4(lx, ly, hy, kk);
+  }
+  return o;
+}
+
+// One wave per (cell, candidate) pair, lanes over the polygon's edges.
+__global__ __launch_bounds__(256) void k_pip_rec_count(const uint32_t *pair_cell,
+                                                       const int32_t *cand_id, int32_t npairs,
+                                                       const int32_t *eoff, const double4 *edge64,
+                                                       const float *k32, double x0, double y0,
+                                                       double cs, int32_t nx, float hb,
+                                                       int2 *cnt) {
+  const uint32_t lane = lane_id();
+  const int32_t nw = (int32_t)(gridDim.x * (blockDim.x / GP_WAVE));
+  for (int32_t k = (int32_t)(blockIdx.x * (blockDim.x / GP_WAVE) + threadIdx.x / GP_WAVE);
+       k < npairs; k += nw) {
+    const uint32_t cell = pair_cell[k];
+    const double cx = x0 + ((double)(cell % (uint32_t)nx) + 0.5) * cs;
+    const double cy = y0 + ((double)(cell / (uint32_t)nx) + 0.5) * cs;
+    const int32_t f = cand_id[k], e1 = eoff[f + 1];
+    int32_t nb = 0, ng = 0;
+    for (int32_t base = eoff[f]; base < e1; base += GP_WAVE) {
+      const int32_t e = base + (int32_t)lane;
+      int cls = -1;
+      if (e < e1) cls = pip_classify(edge64[e], k32[e], cx, cy, hb).cls;
+      nb += __popcll(ballot(cls == PIP_BAND));
+      ng += __popcll(ballot(cls == PIP_GUARDED));
+    }
+    if (lane == 0) cnt[k] = make_int2(nb, ng);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pip_rec_emit(const uint32_t *pair_cell,
+                                                      const int32_t *cand_id, int32_t npairs,
+                                                      const int32_t *eoff, const double4 *edge64,
+                                                      const float *k32, double x0, double y0,
+                                                      double cs, int32_t nx, float hb,
+                                                      const int64_t *off, const int2 *pc,
+                                                      float4 *recs) {
+  const uint32_t lane = lane_id();
+  const uint64_t lt = lanemask_lt();
+  const int32_t nw = (int32_t)(gridDim.x * (blockDim.x / GP_WAVE));
+  for (int32_t k = (int32_t)(blockIdx.x * (blockDim.x / GP_WAVE) + threadIdx.x / GP_WAVE);
+       k < npairs; k += nw) {
+    const uint32_t cell = pair_cell[k];
+    const double cx = x0 + ((double)(cell % (uint32_t)nx) + 0.5) * cs;
+    const double cy = y0 + ((double)(cell / (uint32_t)nx) + 0.5) * cs;
+    const int32_t f = cand_id[k], e1 = eoff[f + 1];
+    const int64_t r0 = off[k], r1 = off[k + 1];
+    const int32_t np = pc[k].x, nb = pc[k].y;
+    const int64_t gs = r0 + ((np + nb + 1) & ~1);
+    if (lane == 0 && ((np + nb) & 1)) recs[r0 + np + nb] = make_float4(0.f, 0.f, 0.f, 0.f);
+    int32_t iP = 0, iB = 0, iG = 0;
+    for (int32_t base = eoff[f]; base < e1; base += GP_WAVE) {
+      const int32_t e = base + (int32_t)lane;
+      PipEdge q;
+      q.cls = -1;
+      if (e < e1) q = pip_classify(edge64[e], k32[e], cx, cy, hb);
+      const uint64_t mP = ballot(q.cls == PIP_PLAIN), mB = ballot(q.cls == PIP_BAND),
+                     mG = ballot(q.cls == PIP_GUARDED);
+      // the classes repeat the counting kernel's bit for bit; the bounds keep every
+      // write inside the pair's slots regardless
+      const int32_t jP = iP + __popcll(mP & lt), jB = iB + __popcll(mB & lt);
+      if (q.cls == PIP_PLAIN && jP < np) recs[r0 + jP] = q.rec;
+      if (q.cls == PIP_BAND && jB < nb) recs[r0 + np + jB] = q.rec;
+      if (q.cls == PIP_GUARDED) {
+        const int64_t g = gs + 2 * (int64_t)(iG + __popcll(mG & lt));
+        if (g + 1 < r1) {
+          recs[g] = q.rec;
+          recs[g + 1] = make_float4(q.G, 0.f, 0.f, 0.f);
+        }
+      }
+      iP += __popcll(mP);
+      iB += __popcll(mB);
+      iG += __popcll(mG);
+    }
+  }
+}
+
+hipError_t launch_pip_rec_count(const uint32_t *pair_cell, const int32_t *cand_id,
+                                int32_t npairs, const int32_t *eoff, const double4 *edge64,
+                                const float *k32, double x0, double y0, double cs, int32_t nx,
+                                float hb, int2 *cnt, hipStream_t s) {
+  if (npairs <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>(((int64_t)npairs + 3) / 4, 65536);
+  hipLaunchKernelGGL(k_pip_rec_count, dim3((unsigned)blocks), dim3(256), 0, s, pair_cell,
+                     cand_id, npairs, eoff, edge64, k32, x0, y0, cs, nx, hb, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_pip_rec_emit(const uint32_t *pair_cell, const int32_t *cand_id,
+                               int32_t npairs, const int32_t *eoff, const double4 *edge64,
+                               const float *k32, double x0, double y0, double cs, int32_t nx,
+                               float hb, const int64_t *off, const int2 *pc, float4 *recs,
+                               hipStream_t s) {
+  if (npairs <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>(((int64_t)npairs + 3) / 4, 65536);
+  hipLaunchKernelGGL(k_pip_rec_emit, dim3((unsigned)blocks), dim3(256), 0, s, pair_cell,
+                     cand_id, npairs, eoff, edge64, k32, x0, y0, cs, nx, hb, off, pc, recs);
+  return hipGetLastError();
+}
+
+// Band test of one edge record: the open straddle 0 < t < h of each lane's point (the
+// crossing), and into amb the lanes with t = 0 or t = h (closed but not open).
+__device__ __forceinline__ uint64_t band_cross(float py, const float4 e, uint64_t &amb) {
+  const uint32_t tb = __float_as_uint(py - e.x);
+  const uint64_t open = ballot(tb - 1u < __float_as_uint(e.y));
+  const uint64_t closed = ballot(tb <= __float_as_uint(e.z));
+  amb |= closed & ~open;
+  return open;
+}
+
+// Mixed PIP refinement of one item from the grid's records: per candidate polygon the
+// records are copied to LDS chunk by chunk and the plain, band and guarded parts of each
+// chunk run their own loops.
+template <int PPL>
+__device__ void pipmix_pre_item(const RefineArgs &a, const Item it, float4 *lds) {
+  if (it.npts <= a.vp_points) {
+    pip_vp_item(a, it);
+    return;
+  }
+  const uint32_t lane = lane_id();
+  const int EC = a.edge_chunk;  // slots per chunk, even
+  const double cx = cell_cx(a, (uint32_t)it.cell), cy = cell_cy(a, (uint32_t)it.cell);
+  float px[PPL], py[PPL];
+  int32_t best[PPL];
+  bool rq[PPL];
+  load_points32<PPL>(a, it, cx, cy, px, py);
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    best[j] = -1;
+    rq[j] = false;
+  }
+  constexpr int U = PPL >= 4 ? 4 : 8;  // plain edges per step
+  const int32_t k0 = a.cand_off[it.cell], k1 = a.cand_off[it.cell + 1];
+  for (int32_t k = k0; k < k1; ++k) {
+    const int32_t f = a.cand_id[k];
+    const int cls = a.cand_class ? a.cand_class[k] : 2;
+    if (cls == 0) continue;  // the cell lies outside polygon f
+    if (cls == 1) {          // inside: every undecided point takes f, and all are decided
+#pragma unroll
+      for (int j = 0; j < PPL; ++j)
+        if (best[j] < 0 && !rq[j]) best[j] = f;
+      break;
+    }
+    const int64_t r0 = a.prec_off[k];
+    const int32_t nsl = (int32_t)(a.prec_off[k + 1] - r0);
+    const int2 pc = a.pcnt[k];
+    const int32_t nP = pc.x, nPB = pc.x + pc.y, gs = (nPB + 1) & ~1;
+    uint64_t par[PPL], flg[PPL];
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) { par[j] = 0; flg[j] = 0; }
+    for (int32_t s = 0; s < nsl; s += EC) {
+      const int cnt = (nsl - s) < EC ? (nsl - s) : EC;
+      __syncthreads();
+      for (int t = (int)lane; t < cnt; t += GP_WAVE) lds[t] = a.precs[r0 + s + t];
+      __syncthreads();
+      auto clampc = [&](int32_t v) { return v < 0 ? 0 : (v > cnt ? cnt : v); };
+      // plain records [0, p1)
+      const int p1 = clampc(nP - s);
+      int t = 0;
+      for (; t + U <= p1; t += U) {
+        float4 e[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) e[q] = lds[t + q];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+          uint64_t m = 0;
+#pragma unroll
+          for (int q = 0; q < U; ++q) m ^= plain_cross(px[j], py[j], e[q]);
+          par[j] ^= m;
+        }
+      }
+      for (; t + 2 <= p1; t += 2) {
+        const float4 e0 = lds[t], e1 = lds[t + 1];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j)
+          par[j] ^= plain_cross(px[j], py[j], e0) ^ plain_cross(px[j], py[j], e1);
+      }
+      if (t < p1) {
+        const float4 e0 = lds[t];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) par[j] ^= plain_cross(px[j], py[j], e0);
+      }
+      // band records [p1, b1)
+      const int b1 = clampc(nPB - s);
+      for (t = p1; t + 4 <= b1; t += 4) {
+        const float4 e0 = lds[t], e1 = lds[t + 1], e2 = lds[t + 2], e3 = lds[t + 3];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+          uint64_t amb = 0;
+          par[j] ^= band_cross(py[j], e0, amb) ^ band_cross(py[j], e1, amb) ^
+                    band_cross(py[j], e2, amb) ^ band_cross(py[j], e3, amb);
+          flg[j] |= amb;
+        }
+      }
+      for (; t < b1; ++t) {
+        const float4 e0 = lds[t];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+          uint64_t amb = 0;
+          par[j] ^= band_cross(py[j], e0, amb);
+          flg[j] |= amb;
+        }
+      }
+      // guarded records, two slots each, from the first even slot after the band ones
+      for (t = clampc(gs - s); t + 2 <= cnt; t += 2) {
+        const float4 e = lds[t];
+        const float G = lds[t + 1].x;
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+          const float ty = py[j] - e.y;
+          const float d = fmaf(ty, e.w, e.x) - px[j];
+          const uint64_t st = ballot(ty >= 0.0f) & ballot(py[j] < e.z);
+          const uint64_t eq = ballot(ty == 0.0f) | ballot(py[j] == e.z);
+          par[j] ^= st & ballot(d > 0.0f);
+          flg[j] |= (eq & ballot(!(d < -G))) | (st & ballot(!(fabsf(d) > G)));
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      const bool odd = (par[j] >> lane) & 1ull;
+      const bool fl = (flg[j] >> lane) & 1ull;
+      if (best[j] < 0 && !rq[j]) {
+        if (fl) rq[j] = true;
+        else if (odd) best[j] = f;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    const int idx = (int)lane + GP_WAVE * j;
+    const bool v = idx < it.npts;
+    if (v && !rq[j]) a.out_id[a.perm[it.pt_lo + idx]] = best[j];
+    push_recheck(a, v && rq[j], (uint32_t)(it.pt_lo + idx));
+  }
+}
+
 // ------------------------------------------------------------------------- P2P staging
 // A chunk holds the segments of consecutive candidate polylines (a polyline longer
 // than the chunk continues in the next one).  tab[q] = (fid, end slot | continues<<31).
@@ -2002,6 +2291,32 @@ __global__ __launch_bounds__(64) void k_pipmix(RefineArgs a, int persistent) {
   }
 }
 
+// Item of a non-persistent launch with XCD locality: workgroup b runs on XCD b mod 8
+// (the hardware places workgroups round-robin), and blocks of GP_XBLOCK consecutive items
+// go round-robin to the XCDs, so the items of one cell share an L2.  A bijection of
+// [0, G) for grids G that are multiples of GP_XCDS * GP_XBLOCK.
+__device__ __forceinline__ uint32_t xcd_item(uint32_t b) {
+  const uint32_t x = b % GP_XCDS, j = b / GP_XCDS;
+  return (j / GP_XBLOCK) * (GP_XCDS * GP_XBLOCK) + x * GP_XBLOCK + j % GP_XBLOCK;
+}
+
+template <int PPL>
+__global__ __launch_bounds__(64) void k_pipmix_pre(RefineArgs a, int persistent) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  float4 *lds = (float4 *)smem;
+  const uint32_t n_items = *a.n_items;
+  uint32_t it = persistent ? next_item(a, n_items) : xcd_item(blockIdx.x);
+  while (it < n_items) {
+    // a cell's last item runs with the fewest points per lane that hold its points
+    const Item item = a.items[it];
+    if (PPL >= 4 && item.npts > 64 && item.npts <= 128) pipmix_pre_item<2>(a, item, lds);
+    else if (PPL >= 2 && item.npts <= 64) pipmix_pre_item<1>(a, item, lds);
+    else pipmix_pre_item<PPL>(a, item, lds);
+    if (!persistent) break;
+    it = next_item(a, n_items);
+  }
+}
+
 // Work-queue pop for a workgroup of several waves (broadcast through LDS).
 __device__ __forceinline__ uint32_t next_item_wg(const RefineArgs &a, uint32_t n_items,
                                                  uint32_t *slot) {
@@ -2071,7 +2386,8 @@ __global__ __launch_bounds__(64 * W) void k_p2pmix_pre(RefineArgs a, int persist
   p2pmix_loop<PPL, W, true>(a, persistent);
 }
 
-static size_t refine_lds_bytes(gp_kind kind, gp_precision prec, int ec, int W) {
+static size_t refine_lds_bytes(gp_kind kind, gp_precision prec, int ec, int W, bool pre) {
+  if (kind == GP_PIP && prec == GP_MIXED && pre) return (size_t)ec * 16;
   if (kind == GP_PIP)
     return prec == GP_FP64 ? (size_t)ec * sizeof(PipRec64) : (size_t)ec * (16 + 16 + 4);
   if (prec == GP_FP64) return (size_t)ec * (sizeof(SegRec64) + sizeof(int2));
@@ -2109,20 +2425,27 @@ hipError_t launch_refine(gp_kind kind, gp_precision prec, const RefineArgs &a,
                          const gp_tuning &t, int num_cu, int64_t max_items, hipStream_t s) {
   const int ppl = t.points_per_lane;
 
+  const bool pip_pre = kind == GP_PIP && prec == GP_MIXED && a.precs != nullptr;
   unsigned grid;
   if (t.persistent) {
     int64_t g = (int64_t)num_cu * t.wg_per_cu;
     if (g > max_items) g = max_items;
     grid = (unsigned)(g < 1 ? 1 : g);
+  } else if (pip_pre) {
+    // xcd_item maps whole blocks of GP_XCDS * GP_XBLOCK workgroups
+    const int64_t blk = GP_XCDS * GP_XBLOCK;
+    grid = (unsigned)(((max_items < 1 ? 1 : max_items) + blk - 1) / blk * blk);
   } else {
     grid = (unsigned)(max_items < 1 ? 1 : max_items);
   }
   const int pers = t.persistent ? 1 : 0;
   const int W = kind == GP_P2P ? t.waves_per_item : 1;
-  const size_t lds = refine_lds_bytes(kind, prec, a.edge_chunk, W);
+  const size_t lds = refine_lds_bytes(kind, prec, a.edge_chunk, W, pip_pre);
   const dim3 blk(64 * W);
   if (kind == GP_PIP && prec == GP_FP64)
     GP_DISPATCH(k_pip64, ppl, dim3(grid), blk, lds, s, a, pers);
+  else if (pip_pre)
+    GP_DISPATCH(k_pipmix_pre, ppl, dim3(grid), blk, lds, s, a, pers);
   else if (kind == GP_PIP)
     GP_DISPATCH(k_pipmix, ppl, dim3(grid), blk, lds, s, a, pers);
   else if (prec == GP_FP64)

@@ -129,15 +129,61 @@ __global__ __launch_bounds__(256) void k_p2p_mix_vregs(uint32_t *out, int iters,
   out[blockIdx.x * blockDim.x + threadIdx.x] = m[0] ^ m[1] ^ m[2] ^ m[3];
 }
 
+// The mixed PIP crossing test on per-lane VGPR data in the refinement loop's shape:
+// PPL points per lane against E edges per step, each test a subtract, an FMA and two
+// compares whose lane masks combine on the scalar unit (AND, then XOR into the parity).
+template <int PPL, int E>
+__global__ __launch_bounds__(256) void k_pip_mix_vregs(uint32_t *out, int iters, float4 e0) {
+  // every edge value differs per lane and per edge, as after an LDS read
+  const uint32_t l = threadIdx.x & 63;
+  const float o = (float)l * 1e-6f;
+  float4 e[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q)
+    e[q] = make_float4(e0.x + o * (float)(q + 1), e0.y - o * (float)(q + 2),
+                       __uint_as_float(0x3f000000u + 4u * l + (uint32_t)q),
+                       e0.w + o * (float)(2 * q + 1));
+  float px[PPL], py[PPL];
+  uint64_t par[PPL];
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    px[j] = threadIdx.x * 1e-4f + 0.25f * j;
+    py[j] = blockIdx.x * 1e-4f - 0.125f * j;
+    par[j] = 0;
+  }
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      uint64_t m = 0;
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const float ty = py[j] - e[q].y;
+        const float xi = fmaf(ty, e[q].w, e[q].x);
+        m ^= __builtin_amdgcn_ballot_w64(__float_as_uint(ty) < __float_as_uint(e[q].z)) &
+             __builtin_amdgcn_ballot_w64(px[j] < xi);
+      }
+      par[j] ^= m;
+      // move the point so nothing is loop-invariant (one add per E tests, about the
+      // loop's LDS address move)
+      py[j] += 1e-7f;
+    }
+  }
+  uint64_t r = 0;
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) r ^= par[j];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = (uint32_t)(r >> (threadIdx.x & 63)) & 1u;
+}
+
 }  // namespace
 
 // which: 0 FP32 FMA on VGPR operands, 1 FP64 FMA, 2 LDS broadcast 16-byte reads, 3 the
 // P2P test on register data with the segment constants in SGPRs, 4 FP32 FMA with an
-// SGPR operand, 5 the P2P test on per-lane VGPR data in the refinement loop's shape.
-// Returns the achieved rate: FLOP/s (0, 1, 4), wave-level broadcast reads per second (2)
-// or tests per second (3, 5).
+// SGPR operand, 5 the P2P test on per-lane VGPR data in the refinement loop's shape, 6 and
+// 7 the PIP crossing test on per-lane VGPR data (2 points per lane x 8 edges per step,
+// 4 points per lane x 4 edges).  Returns the achieved rate: FLOP/s (0, 1, 4), wave-level
+// broadcast reads per second (2) or tests per second (3, 5, 6, 7).
 extern "C" gp_status gp_probe_rate(int32_t which, int32_t iters, double *rate, float *ms) {
-  if (!rate || iters <= 0 || which < 0 || which > 5)
+  if (!rate || iters <= 0 || which < 0 || which > 7)
     return set_error(GP_E_INVALID_ARG, "bad probe arguments");
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -173,6 +219,16 @@ extern "C" gp_status gp_probe_rate(int32_t which, int32_t iters, double *rate, f
       case 2:
         hipLaunchKernelGGL(k_lds_bcast, dim3(blocks), dim3(threads), 0, nullptr, (float *)buf, iters);
         work = nthr / 64.0 * iters * 4;  // wave-level broadcast reads
+        break;
+      case 6:
+        hipLaunchKernelGGL((k_pip_mix_vregs<2, 8>), dim3(blocks), dim3(threads), 0, nullptr,
+                           (uint32_t *)buf, iters, make_float4(0.1f, 0.2f, 0.0f, 0.4f));
+        work = nthr * iters * 16;
+        break;
+      case 7:
+        hipLaunchKernelGGL((k_pip_mix_vregs<4, 4>), dim3(blocks), dim3(threads), 0, nullptr,
+                           (uint32_t *)buf, iters, make_float4(0.1f, 0.2f, 0.0f, 0.4f));
+        work = nthr * iters * 16;
         break;
       case 5:
         hipLaunchKernelGGL(k_p2p_mix_vregs, dim3(blocks), dim3(threads), 0, nullptr,

@@ -48,7 +48,7 @@ class gp_grid_params(Structure):
     _fields_ = [("cell_size", c_double), ("radius_D", c_double), ("x0", c_double),
                 ("y0", c_double), ("nx", c_int64), ("ny", c_int64),
                 ("pip_cell_classes", c_int32), ("p2p_segment_filter", c_int32),
-                ("p2p_prestage", c_int32)]
+                ("prestage", c_int32)]
 
 
 class gp_tuning(Structure):
@@ -211,8 +211,9 @@ def gp_build_grid(kind, geom, params, stream=None) -> Grid:
     ``x``, ``y`` and ``feature_ring_off`` (None for polylines); ``params`` has
     ``cell_size, radius_D, x0, y0, nx, ny`` and optionally ``cell_classes`` (PIP: 1
     classifies every cell/polygon pair at build time), ``segment_filter`` (P2P: 1 keeps
-    per cell only the segments within D of it, for the mixed form) and ``prestage`` (P2P:
-    1 computes every cell's mixed-form segment records at build time)."""
+    per cell only the segments within D of it, for the mixed form) and ``prestage`` (1
+    computes every cell's mixed-form records at build time: P2P segment records, PIP
+    per (cell, polygon) edge records)."""
     k = KINDS.get(kind, kind)
     g, keep = _geometry(geom)
     p = _params(params)

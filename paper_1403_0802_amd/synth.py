@@ -65,7 +65,7 @@ class GridParams:
     ny: int = 0
     cell_classes: int = 0  # PIP: 1 asks the GPU grid to classify cell/polygon pairs
     segment_filter: int = 0  # P2P: 1 asks the GPU grid for per-cell segment lists
-    prestage: int = 0  # P2P: 1 asks the GPU grid for build-time segment records
+    prestage: int = 0  # 1 asks the GPU grid for build-time mixed-form records (both kinds)
 
 
 @dataclasses.dataclass

@@ -64,6 +64,12 @@ def check_p2p(got_id, got_d, want_id, want_d, prec, where=""):
     return float(err.max()) if err.size else 0.0
 
 
+def pip_grid(gp, geom, params, prestage):
+    """A PIP grid as given, or with the build-time mixed-form records (prestage)."""
+    return gp.gp_build_grid("pip", geom, synth.GridParams(**{**params.__dict__,
+                                                            "prestage": prestage}))
+
+
 # ---------------------------------------------------------------------------- pairing
 
 
@@ -125,13 +131,14 @@ def c2():
     return w, want_id, want_d
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_pip_c1(gp, c1, prec):
+@pytest.mark.parametrize("prec,pre", [("fp64", 0), ("mixed", 0), ("mixed", 1)])
+def test_pip_c1(gp, c1, prec, pre):
     w, want = c1
-    say("pip c1", prec)
-    grid = gp.gp_build_grid("pip", w.geom, w.params)
+    say("pip c1", prec, "prestage", pre)
+    grid = pip_grid(gp, w.geom, w.params, pre)
     got, st = run_gpu(gp, grid, w.px, w.py, prec, stats=True)
     assert np.array_equal(got, want), f"{np.sum(got != want)} ids differ"
+    assert st["tests"] == oracle.test_count(oracle.build_grid(w.geom, w.params), w.px, w.py)
     say("  stats", st)
 
 
@@ -151,12 +158,13 @@ def test_golden_fixtures(gp, name, prec):
     """The hand-written closed-form fixtures of tests/golden/, at two cell sizes, with
     the default kernel shapes and with few-point items kept point-parallel."""
     c = golden_cases.load(name)
-    for cs in (1.0, 2.5):
+    for cs, pre in ((1.0, 0), (2.5, 0), (1.0, 1), (2.5, 1)):
         for tuning in (None, dict(points_per_lane=2, vp_points=-1),
                        dict(points_per_lane=4, vp_points=-1)):
-            say("golden", name, prec, cs, tuning)
+            say("golden", name, prec, cs, "prestage", pre, tuning)
             grid = gp.gp_build_grid(c.kind, c.geom, synth.GridParams(cell_size=cs,
-                                                                     radius_D=c.radius))
+                                                                     radius_D=c.radius,
+                                                                     prestage=pre))
             if c.kind == "pip":
                 got = run_gpu(gp, grid, c.px, c.py, prec, tuning=tuning)
                 assert np.array_equal(got, c.want_id), (cs, tuning, got, c.want_id)
@@ -193,7 +201,10 @@ def test_results_invariant_under_tuning(gp, kind):
         w = synth.config2(n_points=200_000, n_lines=4_000, seed_salt=3)
         _, want_id, want_d = oracle.run(w)
     grid = gp.gp_build_grid(kind, w.geom, w.params)
-    for prec in ("fp64", "mixed"):
+    runs = [("fp64", grid), ("mixed", grid)]
+    if kind == "pip":  # and the grid with build-time records
+        runs.append(("mixed", pip_grid(gp, w.geom, w.params, 1)))
+    for prec, grid in runs:
         ref = None
         for t in (TUNINGS_PIP if kind == "pip" else TUNINGS_P2P):
             r = run_gpu(gp, grid, w.px, w.py, prec, tuning=t)
@@ -221,13 +232,15 @@ def test_pip_items_of_every_size(gp):
     say("pip items of every size: points per cell", np.percentile(npc, [5, 50, 95, 100]))
     assert np.any((npc > 16) & (npc <= 64)) and np.any((npc > 64) & (npc <= 128))
     assert np.any(npc > 256)
-    grid = gp.gp_build_grid("pip", w.geom, w.params)
-    for prec in ("fp64", "mixed"):
-        for ppl in (1, 2, 4):
-            for vp in (-1, 16):
-                got = run_gpu(gp, grid, w.px, w.py, prec,
-                              tuning=dict(points_per_lane=ppl, vp_points=vp))
-                assert np.array_equal(got, want), (prec, ppl, vp, int(np.sum(got != want)))
+    for pre in (0, 1):
+        grid = pip_grid(gp, w.geom, w.params, pre)
+        for prec in (("fp64", "mixed") if pre == 0 else ("mixed",)):
+            for ppl in (1, 2, 4):
+                for vp in (-1, 16):
+                    got = run_gpu(gp, grid, w.px, w.py, prec,
+                                  tuning=dict(points_per_lane=ppl, vp_points=vp))
+                    assert np.array_equal(got, want), (prec, pre, ppl, vp,
+                                                       int(np.sum(got != want)))
 
 
 def test_shuffle_invariance(gp):
@@ -311,10 +324,13 @@ def test_points_on_vertices_edges_and_vertex_heights(gp):
     px = np.concatenate([x, mx, lvl_x, np.nextafter(x, 2), np.nextafter(mx, -1), x])
     py = np.concatenate([y, my, y, y, my, np.nextafter(y, 2)])
     want = oracle.pip(g, px, py, oracle.build_grid(g, w.params))
-    grid = gp.gp_build_grid("pip", g, w.params)
-    for prec in ("fp64", "mixed"):
-        got = run_gpu(gp, grid, px, py, prec)
-        assert np.array_equal(got, want), (prec, np.sum(got != want))
+    for pre in (0, 1):
+        grid = pip_grid(gp, g, w.params, pre)
+        for prec in ("fp64", "mixed"):
+            for ppl in (1, 4):
+                got = run_gpu(gp, grid, px, py, prec,
+                              tuning=dict(points_per_lane=ppl, vp_points=-1))
+                assert np.array_equal(got, want), (prec, pre, ppl, np.sum(got != want))
 
 
 def test_holes_overlaps_and_long_rings(gp):
@@ -336,10 +352,12 @@ def test_holes_overlaps_and_long_rings(gp):
     py = np.concatenate([py, 0.05 + 1e-13 * rng.uniform(-1, 2, 20_000)])
     want = oracle.pip(g, px, py, oracle.build_grid(g, params))
     assert np.array_equal(want, oracle.pip(g, px, py))
-    grid = gp.gp_build_grid("pip", g, params)
-    for prec in ("fp64", "mixed"):
-        got = run_gpu(gp, grid, px, py, prec)
-        assert np.array_equal(got, want), (prec, np.sum(got != want))
+    for pre in (0, 1):
+        grid = pip_grid(gp, g, params, pre)
+        for prec in ("fp64", "mixed"):
+            for t in (None, dict(points_per_lane=4, edge_chunk=64)):
+                got = run_gpu(gp, grid, px, py, prec, tuning=t)
+                assert np.array_equal(got, want), (prec, pre, t, np.sum(got != want))
 
 
 # ---------------------------------------------------------------- PIP cell classes
@@ -396,10 +414,15 @@ def test_pip_cell_classes_equal_unclassified(gp, c1, c3_geom, case):
     classed = gp.gp_build_grid("pip", g, cparams)
     info = classed.info()
     assert info["n_pairs_inside"] + info["n_pairs_outside"] + info["n_pairs_boundary"] == info["n_pairs"]
+    # cell classes together with the build-time records
+    both = gp.gp_build_grid("pip", g, synth.GridParams(**{**cparams.__dict__, "prestage": 1}))
+    r_both, st_both = run_gpu(gp, both, px, py, "mixed", stats=True)
     for prec in ("fp64", "mixed"):
         ref, st0 = run_gpu(gp, plain, px, py, prec, stats=True)
         got, st1 = run_gpu(gp, classed, px, py, prec, stats=True)
         assert np.array_equal(got, ref), (case, prec, np.sum(got != ref))
+        assert np.array_equal(r_both, ref), (case, "classes + prestage", np.sum(r_both != ref))
+        assert st_both["tests"] == st1["tests"]
         if want is not None:
             assert np.array_equal(got, want), (case, prec)
         assert st0["tests_avoided"] == 0
@@ -590,9 +613,13 @@ def test_near_edge_sweep_mixed(gp):
     grid = gp.gp_build_grid("pip", geom, params)
     got64 = run_gpu(gp, grid, px, py, "fp64")
     assert np.array_equal(got64, want)
-    got, st = run_gpu(gp, grid, px, py, "mixed", stats=True)
-    assert np.array_equal(got, want), np.sum(got != want)
-    say("  rechecked", st["n_rechecked"], "of", len(px))
+    for pre in (0, 1):
+        grid = pip_grid(gp, geom, params, pre)
+        for ppl in (1, 2, 4):
+            got, st = run_gpu(gp, grid, px, py, "mixed", stats=True,
+                              tuning=dict(points_per_lane=ppl, vp_points=-1))
+            assert np.array_equal(got, want), (pre, ppl, np.sum(got != want))
+            say("  prestage", pre, "ppl", ppl, "rechecked", st["n_rechecked"], "of", len(px))
 
 
 def test_p2p_ties_range_and_degenerate_segments(gp):
@@ -773,6 +800,9 @@ def test_c3_mixed_equals_fp64_and_oracle_sample(gp, c3_geom):
     g64, s64 = run_gpu(gp, grid, px, py, "fp64", stats=True)
     gmx, smx = run_gpu(gp, grid, px, py, "mixed", stats=True)
     assert np.array_equal(g64, gmx), np.sum(g64 != gmx)
+    gpre, spre = run_gpu(gp, pip_grid(gp, geom, params, 1), px, py, "mixed", stats=True)
+    assert np.array_equal(g64, gpre), np.sum(g64 != gpre)
+    assert spre["tests"] == s64["tests"]
     idx = np.random.default_rng(0).choice(len(px), 20_000, replace=False)
     og = oracle.build_grid(geom, params)
     want = oracle.pip(geom, px[idx], py[idx], og)
