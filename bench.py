@@ -81,10 +81,10 @@ def write_traffic(fetch_csv: str, write_csv: str):
         per[counter] = {"copy_factor": factor}
         for r in rows:
             name = r["Kernel_Name"]
-            for k in ("k_p2pmix_pre", "k_p2pmix", "k_pipmix", "k_p2p64", "k_pip64"):
+            for k in ("k_p2pmix_pre", "k_p2pmix", "k_pipmix_pre", "k_pipmix", "k_p2p64", "k_pip64"):
                 if f"gp::{k}<" in name:
                     per[counter].setdefault(k, []).append(float(r["Counter_Value"]))
-    for k in ("k_p2pmix_pre", "k_p2pmix", "k_pipmix", "k_p2p64", "k_pip64"):
+    for k in ("k_p2pmix_pre", "k_p2pmix", "k_pipmix_pre", "k_pipmix", "k_p2p64", "k_pip64"):
         f = per["FETCH_SIZE"].get(k)
         w = per["WRITE_SIZE"].get(k)
         ff, wf = per["FETCH_SIZE"]["copy_factor"], per["WRITE_SIZE"]["copy_factor"]
@@ -105,10 +105,11 @@ def write_traffic(fetch_csv: str, write_csv: str):
 
 WORKLOAD_NAME = "C3 PIP 50M pts x 5000 polygons + C4 P2P 200M pts x 200000 polylines, mixed"
 # The grids of the step (the full-size parity tests build the same ones).  PIP: 1/512, the
-# fastest PIP query of the cell-size sweep (bench.py --cell-sweep).  P2P: 100 m cells with
+# fastest PIP query of the cell-size sweep (bench.py --cell-sweep), with build-time
+# per-(cell, polygon) edge records (prestage).  P2P: 100 m cells with
 # build-time segment records (p2p_prestage), an index structure like the candidate lists;
 # detail.p2p_plain_grid runs the grid without them.
-PIP_GRID = dict(cell_size=1 / 512, nx=512, ny=512)
+PIP_GRID = dict(cell_size=1 / 512, nx=512, ny=512, prestage=1)
 P2P_GRID = dict(cell_size=100.0, radius_D=100.0, nx=400, ny=400, prestage=1)
 
 
@@ -465,7 +466,8 @@ def main():
     p2p_flops = tests_p2p * F_P2P / (p2p_ref / 1e3)
     dom = "p2p" if p2p_ref >= pip_ref else "pip"
     p2p_kernel = "k_p2pmix_pre" if getattr(p4, "prestage", 0) else "k_p2pmix"
-    dom_kernel = p2p_kernel if dom == "p2p" else "k_pipmix"
+    pip_kernel = "k_pipmix_pre" if getattr(p3, "prestage", 0) else "k_pipmix"
+    dom_kernel = p2p_kernel if dom == "p2p" else pip_kernel
     achieved = p2p_flops if dom == "p2p" else pip_flops
     workload = WORKLOAD_NAME
     if args.scale != 1.0:
@@ -617,8 +619,10 @@ def main():
                    "p2p_points": detail["p2p"]["points"], "pip_polygons": geom3.n_features,
                    "p2p_polylines": geom4.n_features, "radius_D_m": 100.0,
                    "pip_grid": {"cell_size": p3.cell_size, "nx": p3.nx, "ny": p3.ny,
+                                "prestage": int(getattr(p3, "prestage", 0)),
                                 "note": "1/512 cells, the fastest PIP query of the cell-size "
-                                        "sweep (the survey's C3 grid is 1/1024)"},
+                                        "sweep (the survey's C3 grid is 1/1024), with "
+                                        "build-time per-(cell, polygon) edge records"},
                    "p2p_grid": {"cell_size_m": p4.cell_size, "nx": p4.nx, "ny": p4.ny,
                                 "prestage": int(getattr(p4, "prestage", 0)),
                                 "note": "with build-time per-(cell, segment) FP32 records"},

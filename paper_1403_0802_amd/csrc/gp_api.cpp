@@ -426,6 +426,14 @@ extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
         off[k + 1] = off[k] + ((np + nb + 1) & ~1) + 2 * (int64_t)ng;
       }
       g->nprec = off[npairs];
+      {
+        // the refinement addresses a cell's records relative to its first one in 32 bits
+        std::vector<int32_t> co((size_t)ncells + 1);
+        GP_TRY_HIP_G(hipMemcpy(co.data(), g->d_cand_off, co.size() * 4, hipMemcpyDeviceToHost));
+        for (size_t c = 0; c < (size_t)ncells; ++c)
+          if (off[(size_t)co[c + 1]] - off[(size_t)co[c]] >= kMaxCount)
+            return fail(set_error(GP_E_CAPACITY, "cell %zu holds 2^31 or more PIP records", c));
+      }
       GP_TRY_HIP_G(hipMalloc(&g->d_prec_off, off.size() * 8));
       GP_TRY_HIP_G(hipMalloc(&g->d_pcnt, (size_t)npairs * sizeof(int2)));
       if (hipMalloc(&g->d_precs, (size_t)std::max<int64_t>(g->nprec, 1) * sizeof(float4)) !=
@@ -603,7 +611,8 @@ size_t workspace_layout(const Grid &g, int64_t n, gp_precision prec, void *base,
     return base ? (void *)((char *)base + o) : nullptr;
   };
   const size_t un = (size_t)std::max<int64_t>(n, 1);
-  const size_t hist = radix_hist_elems(un);
+  const size_t mi = (size_t)max_items(g, n);
+  const size_t hist = radix_hist_elems(std::max(un, mi));
   const size_t nc1 = (size_t)g.ncells + 1;
   Workspace w;
   w.keyA = (uint32_t *)take(un * 4);
@@ -614,7 +623,17 @@ size_t workspace_layout(const Grid &g, int64_t n, gp_precision prec, void *base,
   w.scan_tmp = (uint32_t *)take(scan_tmp_elems(std::max(hist, nc1)) * 4);
   w.pt_off = (int32_t *)take(nc1 * 4);
   w.item_cnt = (uint32_t *)take(nc1 * 4);
-  w.items = (Item *)take((size_t)max_items(g, n) * sizeof(Item));
+  w.items = (Item *)take(mi * sizeof(Item));
+  if (g.kind == GP_PIP) {
+    w.ikA = (uint32_t *)take(mi * 4);
+    w.ikB = (uint32_t *)take(mi * 4);
+    w.ivA = (uint32_t *)take(mi * 4);
+    w.ivB = (uint32_t *)take(mi * 4);
+    w.items_sorted = (Item *)take(mi * sizeof(Item));
+  } else {
+    w.ikA = w.ikB = w.ivA = w.ivB = nullptr;
+    w.items_sorted = nullptr;
+  }
   w.counters = (uint32_t *)take(C_COUNT * 4);
   w.tests = (unsigned long long *)take(16);
   w.xyA = (double2 *)take(un * 16);
@@ -747,9 +766,16 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
                           segf ? g->d_cell_edges : g->d_cell_edges_all, g->ncells,
                           64 * t.points_per_lane * t.waves_per_item, w.item_cnt, w.scan_tmp,
                           w.items, w.counters, w.tests, s));
-  if (stats) GP_TRY_HIP(hipEventRecord(ev[1], s));
   const int64_t mi = n / (64 * t.points_per_lane * t.waves_per_item) +
                     std::min<int64_t>(g->ncells, n) + 1;
+  if (kind == GP_PIP) {
+    // PIP items run one workgroup each: longest first, so the items of cells under the
+    // largest polygons start early and the launch does not end on them
+    GP_TRY_HIP(launch_order_items(w.items, a.n_items, mi, g->d_cell_edges, w.ikA, w.ikB, w.ivA,
+                                  w.ivB, w.hist, w.scan_tmp, w.items_sorted, s));
+    a.items = w.items_sorted;
+  }
+  if (stats) GP_TRY_HIP(hipEventRecord(ev[1], s));
   GP_TRY_HIP(launch_refine(kind, prec, a, t, g->num_cu, mi, s));
   if (stats) GP_TRY_HIP(hipEventRecord(ev[2], s));
   if (prec == GP_MIXED) GP_TRY_HIP(launch_recheck(kind, a, g->num_cu, s));

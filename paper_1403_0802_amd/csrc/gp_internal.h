@@ -20,7 +20,8 @@ struct Item {
   int32_t cell;
   int32_t pt_lo;
   int32_t npts;
-  int32_t cost_rank;  // spare: cost bucket used to order the queue
+  int32_t cost_rank;  // PIP: cost bucket (4 per octave of npts * cell edges) of the
+                      // longest-first order
 };
 
 // Everything the refinement kernels read.  Passed by value as the kernel argument.
@@ -120,6 +121,8 @@ struct Workspace {
   double2 *xyA, *xyB;    // FP64 point payload of the sort (ping-pong)
   uint32_t *item_cnt;    // [ncells+1] -> exclusive offsets
   Item *items;
+  uint32_t *ikA, *ikB, *ivA, *ivB;  // PIP: sort of the items by cost (max_items each)
+  Item *items_sorted;
   uint32_t *rq;
   uint32_t *counters;    // [16]: 0 item counter, 1 rq count, 2 n_items(copy), ...
   unsigned long long *tests;  // [1]
@@ -210,6 +213,11 @@ hipError_t launch_items(const int32_t *pt_off, const int32_t *cand_off,
                         int32_t ncells, int32_t chunk,
                         uint32_t *item_cnt, uint32_t *scan_tmp, Item *items, uint32_t *counters,
                         unsigned long long *tests, hipStream_t s);
+// Items in longest-first order into out[0 .. *n_items), with their cost buckets.
+hipError_t launch_order_items(Item *items, const uint32_t *n_items, int64_t max_items,
+                              const int64_t *cell_edges, uint32_t *kA, uint32_t *kB,
+                              uint32_t *vA, uint32_t *vB, uint32_t *hist, uint32_t *scan_tmp,
+                              Item *out, hipStream_t s);
 hipError_t launch_refine(gp_kind kind, gp_precision prec, const RefineArgs &a,
                          const gp_tuning &t, int num_cu, int64_t max_items, hipStream_t s);
 hipError_t launch_recheck(gp_kind kind, const RefineArgs &a, int num_cu, hipStream_t s);

@@ -966,6 +966,59 @@ hipError_t launch_items(const int32_t *pt_off, const int32_t *cand_off,
   return hipGetLastError();
 }
 
+// Longest-first order of the items (the classic rule for scheduling jobs of unequal
+// length on parallel machines): a cost bucket per item, 4 per octave of its test count
+// npts * cell_edges, kept in Item::cost_rank; sort keys put large buckets first and the
+// slots beyond the item count (key 255) last.
+__device__ __forceinline__ uint32_t cost_bucket(uint64_t c) {
+  if (c == 0) return 0;
+  const uint32_t e = 63u - (uint32_t)__clzll(c);  // floor(log2 c)
+  const uint32_t frac = e >= 2 ? (uint32_t)(c >> (e - 2)) & 3u : (uint32_t)(c << (2 - e)) & 3u;
+  const uint32_t b = 4u * e + frac;
+  return b < 254u ? b : 254u;
+}
+
+__global__ void k_item_keys(Item *items, const uint32_t *n_items, int64_t max_items,
+                            const int64_t *cell_edges, uint32_t *keys) {
+  const uint32_t n = *n_items;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < max_items;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t key = 255u;
+    if (i < (int64_t)n) {
+      Item it = items[i];
+      const uint32_t b = cost_bucket((uint64_t)it.npts * (uint64_t)cell_edges[it.cell]);
+      items[i].cost_rank = (int32_t)b;
+      key = 254u - b;
+    }
+    keys[i] = key;
+  }
+}
+
+__global__ void k_item_gather(const Item *items, const uint32_t *idx, int64_t max_items,
+                              const uint32_t *n_items, Item *out) {
+  const uint32_t n = *n_items;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = items[idx[i]];
+}
+
+hipError_t launch_order_items(Item *items, const uint32_t *n_items, int64_t max_items,
+                              const int64_t *cell_edges, uint32_t *kA, uint32_t *kB,
+                              uint32_t *vA, uint32_t *vB, uint32_t *hist, uint32_t *scan_tmp,
+                              Item *out, hipStream_t s) {
+  if (max_items <= 0) return hipSuccess;
+  const unsigned g = grid_for((size_t)max_items, 256, 8192);
+  hipLaunchKernelGGL(k_item_keys, dim3(g), dim3(256), 0, s, items, n_items, max_items,
+                     cell_edges, kA);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  uint32_t *ks = nullptr, *vs = nullptr;
+  e = launch_radix_sort(kA, kB, vA, vB, (size_t)max_items, 8, true, hist, scan_tmp, s, &ks, &vs);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_item_gather, dim3(g), dim3(256), 0, s, items, vs, max_items, n_items, out);
+  return hipGetLastError();
+}
+
 __global__ void k_copy_perm(const uint32_t *perm, int64_t n, int32_t *out) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -1539,8 +1592,29 @@ __device__ void pipmix_pre_item(const RefineArgs &a, const Item it, float4 *lds)
   }
   constexpr int U = PPL >= 4 ? 4 : 8;  // plain edges per step
   const int32_t k0 = a.cand_off[it.cell], k1 = a.cand_off[it.cell + 1];
+  // the metadata of the cell's first 64 candidate pairs, one pair per lane, in one round
+  // trip, kept in LDS after the chunk: polygon id, first record slot relative to the
+  // cell's first, (plain, band) counts
+  int4 *meta = (int4 *)(lds + a.edge_chunk);
+  const int64_t rbase = a.prec_off[k0], rend = a.prec_off[k1];
+  if ((int)lane < k1 - k0) {
+    const int32_t k = k0 + (int32_t)lane;
+    const int2 pc = a.pcnt[k];
+    meta[lane] = make_int4(a.cand_id[k], (int32_t)(a.prec_off[k] - rbase), pc.x, pc.y);
+  }
+  __syncthreads();
   for (int32_t k = k0; k < k1; ++k) {
-    const int32_t f = a.cand_id[k];
+    const int32_t q = k - k0;
+    const bool inreg = q < GP_WAVE;
+    int4 m = make_int4(0, 0, 0, 0);
+    if (inreg) {
+      m = meta[q];
+      m.x = __builtin_amdgcn_readfirstlane(m.x);
+      m.y = __builtin_amdgcn_readfirstlane(m.y);
+      m.z = __builtin_amdgcn_readfirstlane(m.z);
+      m.w = __builtin_amdgcn_readfirstlane(m.w);
+    }
+    const int32_t f = inreg ? m.x : a.cand_id[k];
     const int cls = a.cand_class ? a.cand_class[k] : 2;
     if (cls == 0) continue;  // the cell lies outside polygon f
     if (cls == 1) {          // inside: every undecided point takes f, and all are decided
@@ -1549,10 +1623,14 @@ __device__ void pipmix_pre_item(const RefineArgs &a, const Item it, float4 *lds)
         if (best[j] < 0 && !rq[j]) best[j] = f;
       break;
     }
-    const int64_t r0 = a.prec_off[k];
-    const int32_t nsl = (int32_t)(a.prec_off[k + 1] - r0);
-    const int2 pc = a.pcnt[k];
-    const int32_t nP = pc.x, nPB = pc.x + pc.y, gs = (nPB + 1) & ~1;
+    const int64_t r0 = inreg ? rbase + m.y : a.prec_off[k];
+    const int64_t r1 = k + 1 == k1 ? rend
+                       : (q + 1 < GP_WAVE ? rbase + __builtin_amdgcn_readfirstlane(meta[q + 1].y)
+                                          : a.prec_off[k + 1]);
+    const int32_t nsl = (int32_t)(r1 - r0);
+    const int32_t nP = inreg ? m.z : a.pcnt[k].x;
+    const int32_t nPB = nP + (inreg ? m.w : a.pcnt[k].y);
+    const int32_t gs = (nPB + 1) & ~1;
     uint64_t par[PPL], flg[PPL];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) { par[j] = 0; flg[j] = 0; }
@@ -2300,6 +2378,15 @@ __device__ __forceinline__ uint32_t xcd_item(uint32_t b) {
   return (j / GP_XBLOCK) * (GP_XCDS * GP_XBLOCK) + x * GP_XBLOCK + j % GP_XBLOCK;
 }
 
+// Wave priority of an item from its cost bucket (4 per octave of tests): the few items of
+// 2^18 tests and more -- cells under the largest polygons -- take the SIMD's issue slots
+// first, so they end with the bulk instead of after it.
+__device__ __forceinline__ void item_priority(const Item &it) {
+  if (it.cost_rank >= 4 * 22) __builtin_amdgcn_s_setprio(3);
+  else if (it.cost_rank >= 4 * 20) __builtin_amdgcn_s_setprio(2);
+  else if (it.cost_rank >= 4 * 18) __builtin_amdgcn_s_setprio(1);
+}
+
 template <int PPL>
 __global__ __launch_bounds__(64) void k_pipmix_pre(RefineArgs a, int persistent) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -2309,9 +2396,11 @@ __global__ __launch_bounds__(64) void k_pipmix_pre(RefineArgs a, int persistent)
   while (it < n_items) {
     // a cell's last item runs with the fewest points per lane that hold its points
     const Item item = a.items[it];
+    item_priority(item);
     if (PPL >= 4 && item.npts > 64 && item.npts <= 128) pipmix_pre_item<2>(a, item, lds);
     else if (PPL >= 2 && item.npts <= 64) pipmix_pre_item<1>(a, item, lds);
     else pipmix_pre_item<PPL>(a, item, lds);
+    __builtin_amdgcn_s_setprio(0);
     if (!persistent) break;
     it = next_item(a, n_items);
   }
@@ -2387,7 +2476,7 @@ __global__ __launch_bounds__(64 * W) void k_p2pmix_pre(RefineArgs a, int persist
 }
 
 static size_t refine_lds_bytes(gp_kind kind, gp_precision prec, int ec, int W, bool pre) {
-  if (kind == GP_PIP && prec == GP_MIXED && pre) return (size_t)ec * 16;
+  if (kind == GP_PIP && prec == GP_MIXED && pre) return (size_t)ec * 16 + GP_WAVE * 16;
   if (kind == GP_PIP)
     return prec == GP_FP64 ? (size_t)ec * sizeof(PipRec64) : (size_t)ec * (16 + 16 + 4);
   if (prec == GP_FP64) return (size_t)ec * (sizeof(SegRec64) + sizeof(int2));
