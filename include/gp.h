@@ -143,9 +143,11 @@ typedef struct gp_tuning {
                                 0: one workgroup per item */
     int32_t waves_per_item;  /* P2P: 1, 2 or 4 wavefronts share one LDS staging and a work
                                 item holds up to 64*ppl*waves points; PIP: always 1 */
-    int32_t vp_points;       /* PIP: items with at most this many points (1..64) use the
-                                vertex-parallel mapping (lanes over edges, FP64, Sec.
-                                III.B's alternative); -1 never; 0 = library default */
+    int32_t vp_points;       /* items with at most this many points (1..64) use the
+                                vertex-parallel mapping (lanes over edges or segments, the
+                                wave looping over the points; FP64, Sec. III.B's
+                                alternative; P2P: one-wave items only); -1 never;
+                                0 = library default (PIP 16, P2P 4) */
 } gp_tuning;
 
 /* Per-call counters.  Filling them synchronises the stream at the end of the call. */
@@ -233,10 +235,23 @@ gp_status gp_get_tuning(const gp_grid *grid, gp_precision prec, gp_tuning *tunin
 
 /* Autotuner: times every configuration of a built-in search space on the given
  * (device) sample points, keeps the fastest, stores it in the grid and returns it.
- * Results never depend on the configuration.  Synchronous. */
+ * Results never depend on the configuration.  The winner is cached in the process by
+ * (operation, precision, GPU architecture, the grid's build-time options, workload class:
+ * the octaves of the sample size, of the tests per paired point and of the paired points
+ * per work item under the library default); a later call whose key is cached applies
+ * that winner without searching.  Synchronous. */
 gp_status gp_autotune(gp_grid *grid, gp_precision prec, int64_t n, const double *px,
                       const double *py, void *ws, size_t ws_bytes, void *hip_stream,
                       gp_tuning *best, float *best_ms);
+
+/* The autotuner's cache: entries in the process, written to / merged from a text file (one
+ * line per entry: key, tab, the six gp_tuning fields), so deployments reuse earlier
+ * searches.  gp_tuning_cache_load adds nothing and returns GP_E_INVALID_ARG when a line is
+ * malformed or holds an invalid tuning. */
+gp_status gp_tuning_cache_save(const char *path);
+gp_status gp_tuning_cache_load(const char *path);
+gp_status gp_tuning_cache_clear(void);
+gp_status gp_tuning_cache_size(int64_t *entries);
 
 /* Cell-size sweep: the filter-versus-refine trade-off that Sec. III.A leaves open (a
  * finer grid pairs fewer features with each point but costs more pairs and memory).

@@ -7,6 +7,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "gp_internal.h"
@@ -61,13 +64,14 @@ struct DevBuf {
 }  // namespace
 
 // Defaults from full-size sweeps on the configuration-3/4 workloads (gp_autotune
-// re-tunes): P2P 4 points per lane from a persistent queue (the FP64 form with 64-segment
-// chunks: its 64-byte LDS records otherwise limit the waves per CU), PIP 2 points per lane
-// and one workgroup per item (the per-item edge staging is shared by 128 points).
+// re-tunes): P2P from a persistent queue, the mixed form with 4 points per lane, the FP64
+// form with 2 (it carries three doubles per point from segment to segment) and 64-segment
+// chunks (its 64-byte LDS records otherwise limit the waves per CU); PIP 2 points per lane
+// and one workgroup per item.
 static gp_tuning default_tuning(gp_kind kind, gp_precision prec) {
   gp_tuning t;
   if (kind == GP_P2P) {
-    t.points_per_lane = 4;
+    t.points_per_lane = prec == GP_MIXED ? 4 : 2;
     t.edge_chunk = prec == GP_MIXED ? 128 : 64;
     t.wg_per_cu = 32;
     t.persistent = 1;
@@ -78,7 +82,10 @@ static gp_tuning default_tuning(gp_kind kind, gp_precision prec) {
     t.persistent = 0;
   }
   t.waves_per_item = 1;
-  t.vp_points = kind == GP_PIP ? 16 : -1;
+  // few-point items vertex-parallel: PIP up to 16 points (its FP64 edge test is cheap
+  // next to the staging a point-parallel item needs), P2P up to 4 (each point's polyline
+  // minimum is a serial cross-lane reduction)
+  t.vp_points = kind == GP_PIP ? 16 : 4;
   return t;
 }
 
@@ -88,7 +95,7 @@ static bool tuning_valid(const gp_tuning &t, gp_kind kind) {
          t.edge_chunk >= 64 && t.edge_chunk <= 512 && t.edge_chunk % 64 == 0 &&
          t.wg_per_cu >= 1 && t.wg_per_cu <= 32 && (t.persistent == 0 || t.persistent == 1) &&
          (w == 1 || (kind == GP_P2P && (w == 2 || w == 4))) &&
-         (t.vp_points == -1 || (kind == GP_PIP && t.vp_points >= 1 && t.vp_points <= 64));
+         (t.vp_points == -1 || (t.vp_points >= 1 && t.vp_points <= 64));
 }
 
 // ------------------------------------------------------------------------- geometry checks
@@ -880,8 +887,132 @@ extern "C" gp_status gp_get_tuning(const gp_grid *g, gp_precision prec, gp_tunin
   return GP_OK;
 }
 
+// ------------------------------------------------------------------------- tuning cache
+// Winners of gp_autotune by (operation, precision, GPU architecture, grid records, workload
+// class); the class is the octave of the sample size, of the tests per paired point and of
+// the paired points per work item under the library default tuning.  A text line per entry:
+// the key, a tab, then points_per_lane edge_chunk wg_per_cu persistent waves_per_item
+// vp_points.
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, gp_tuning> g_tune_cache;
+
+int octave(double v) { return v >= 1.0 ? (int)std::floor(std::log2(v)) : 0; }
+}  // namespace
+
+static std::string device_arch(int dev) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+static std::string tune_key(const Grid &g, gp_precision prec, int64_t n, const gp_stats &st) {
+  char buf[256];
+  const double paired = (double)std::max<int64_t>(st.n_paired, 1);
+  snprintf(buf, sizeof(buf), "%s %s %s rec=%d seg=%d cls=%d n=%d tpp=%d ppi=%d",
+           g.kind == GP_PIP ? "pip" : "p2p", prec == GP_MIXED ? "mixed" : "fp64",
+           device_arch(g.device).c_str(), (g.d_precs || g.d_recU) ? 1 : 0,
+           g.d_cseg_off ? 1 : 0, g.d_cand_class ? 1 : 0, octave((double)n),
+           octave((double)st.tests / paired), octave(paired / (double)std::max<int64_t>(st.n_items, 1)));
+  return buf;
+}
+
+extern "C" gp_status gp_tuning_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache.clear();
+  return GP_OK;
+}
+
+extern "C" gp_status gp_tuning_cache_size(int64_t *entries) {
+  if (!entries) return set_error(GP_E_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  *entries = (int64_t)g_tune_cache.size();
+  return GP_OK;
+}
+
+extern "C" gp_status gp_tuning_cache_save(const char *path) {
+  if (!path) return set_error(GP_E_INVALID_ARG, "null path");
+  FILE *f = fopen(path, "w");
+  if (!f) return set_error(GP_E_INVALID_ARG, "cannot write %s", path);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto &kv : g_tune_cache) {
+    const gp_tuning &t = kv.second;
+    fprintf(f, "%s\t%d %d %d %d %d %d\n", kv.first.c_str(), t.points_per_lane, t.edge_chunk,
+            t.wg_per_cu, t.persistent, t.waves_per_item, t.vp_points);
+  }
+  const bool ok = fclose(f) == 0;
+  return ok ? GP_OK : set_error(GP_E_INVALID_ARG, "cannot write %s", path);
+}
+
+// Adds the file's entries to the cache (replacing equal keys).  Nothing is added when a
+// line is malformed or holds an invalid tuning.
+extern "C" gp_status gp_tuning_cache_load(const char *path) {
+  if (!path) return set_error(GP_E_INVALID_ARG, "null path");
+  FILE *f = fopen(path, "r");
+  if (!f) return set_error(GP_E_INVALID_ARG, "cannot read %s", path);
+  std::map<std::string, gp_tuning> add;
+  char line[512];
+  int lineno = 0;
+  gp_status st = GP_OK;
+  while (fgets(line, sizeof(line), f)) {
+    ++lineno;
+    std::string l(line);
+    while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+    if (l.empty()) continue;
+    const size_t tab = l.find('\t');
+    gp_tuning t;
+    char tail = 0;
+    if (tab == std::string::npos || tab == 0 ||
+        sscanf(l.c_str() + tab + 1, "%d %d %d %d %d %d %c", &t.points_per_lane, &t.edge_chunk,
+               &t.wg_per_cu, &t.persistent, &t.waves_per_item, &t.vp_points, &tail) != 6) {
+      st = set_error(GP_E_INVALID_ARG, "%s:%d: malformed tuning cache line", path, lineno);
+      break;
+    }
+    const std::string key = l.substr(0, tab);
+    const gp_kind kind = key.rfind("pip ", 0) == 0 ? GP_PIP : key.rfind("p2p ", 0) == 0 ? GP_P2P
+                                                                                       : (gp_kind)0;
+    if (!kind || !tuning_valid(t, kind)) {
+      st = set_error(GP_E_INVALID_ARG, "%s:%d: invalid tuning cache entry", path, lineno);
+      break;
+    }
+    add[key] = t;
+  }
+  fclose(f);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto &kv : add) g_tune_cache[kv.first] = kv.second;
+  return GP_OK;
+}
+
+static gp_status autotune_search(gp_grid *g, gp_precision prec, int64_t n, const double *px,
+                                 const double *py, int32_t *id, double *dist, void *ws,
+                                 size_t ws_bytes, hipStream_t s, gp_tuning *best,
+                                 float *best_ms);
+
+// Median of three timed queries (after one untimed) of one configuration.
+static gp_status time_config(gp_grid *g, gp_precision prec, int64_t n, const double *px,
+                             const double *py, int32_t *id, double *dist, void *ws,
+                             size_t ws_bytes, hipStream_t s, const gp_tuning &t, float *ms,
+                             gp_stats *first) {
+  float times[3];
+  for (int r = 0; r < 4; ++r) {
+    gp_stats st;
+    gp_status rc = run_query(g, g->kind, n, px, py, id, dist, prec, ws, ws_bytes, s, &st, &t);
+    if (rc) return rc;
+    if (r == 0 && first) *first = st;
+    if (r > 0) times[r - 1] = st.ms_total;
+  }
+  std::sort(times, times + 3);
+  *ms = times[1];
+  return GP_OK;
+}
+
 // Grid search over points per lane, LDS edge chunk, persistent workgroups per CU and the
 // queue mode; each configuration is timed (median of 3 after one warm-up) on the sample.
+// A cached winner for the sample's workload class is taken without the search.
 extern "C" gp_status gp_autotune(gp_grid *g, gp_precision prec, int64_t n, const double *px,
                                  const double *py, void *ws, size_t ws_bytes, void *hip_stream,
                                  gp_tuning *best, float *best_ms) {
@@ -892,6 +1023,48 @@ extern "C" gp_status gp_autotune(gp_grid *g, gp_precision prec, int64_t n, const
   DevBuf d_id, d_dist;
   GP_TRY_HIP(d_id.alloc((size_t)n * 4));
   GP_TRY_HIP(d_dist.alloc((size_t)n * 8));
+  {
+    // the workload class, from a query with the library default
+    const gp_tuning def = default_tuning(g->kind, prec);
+    gp_stats st0;
+    float ms0 = 0.f;
+    gp_status rc = time_config(g, prec, n, px, py, d_id.as<int32_t>(), d_dist.as<double>(), ws,
+                               ws_bytes, s, def, &ms0, &st0);
+    if (rc) return rc;
+    const std::string key = tune_key(*g, prec, n, st0);
+    gp_tuning hit;
+    bool found = false;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) {
+        hit = it->second;
+        found = true;
+      }
+    }
+    if (found) {
+      float ms = 0.f;
+      rc = time_config(g, prec, n, px, py, d_id.as<int32_t>(), d_dist.as<double>(), ws,
+                       ws_bytes, s, hit, &ms, nullptr);
+      if (rc) return rc;
+      g->tune[prec] = hit;
+      if (best) *best = hit;
+      if (best_ms) *best_ms = ms;
+      return GP_OK;
+    }
+    rc = autotune_search(g, prec, n, px, py, d_id.as<int32_t>(), d_dist.as<double>(), ws,
+                         ws_bytes, s, best, best_ms);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = g->tune[prec];
+    return GP_OK;
+  }
+}
+
+static gp_status autotune_search(gp_grid *g, gp_precision prec, int64_t n, const double *px,
+                                 const double *py, int32_t *id, double *dist, void *ws,
+                                 size_t ws_bytes, hipStream_t s, gp_tuning *best,
+                                 float *best_ms) {
   std::vector<gp_tuning> space;
   const int ppls[3] = {1, 2, 4}, ecs[3] = {128, 256, 512}, wgs[4] = {8, 12, 16, 32};
   for (int p : ppls)
@@ -908,39 +1081,28 @@ extern "C" gp_status gp_autotune(gp_grid *g, gp_precision prec, int64_t n, const
   for (gp_tuning &t : space) t.vp_points = vp_default;
   float best_t = INFINITY;
   gp_tuning best_cfg = g->tune[prec];
-  for (const gp_tuning &t : space) {
-    float times[3];
-    for (int r = 0; r < 4; ++r) {
-      gp_stats st;
-      gp_status rc = run_query(g, g->kind, n, px, py, d_id.as<int32_t>(), d_dist.as<double>(),
-                               prec, ws, ws_bytes, s, &st, &t);
-      if (rc) return rc;
-      if (r > 0) times[r - 1] = st.ms_total;
-    }
-    std::sort(times, times + 3);
-    if (times[1] < best_t) {
-      best_t = times[1];
+  auto consider = [&](const gp_tuning &t) -> gp_status {
+    float ms = 0.f;
+    gp_status rc = time_config(g, prec, n, px, py, id, dist, ws, ws_bytes, s, t, &ms, nullptr);
+    if (!rc && ms < best_t) {
+      best_t = ms;
       best_cfg = t;
     }
+    return rc;
+  };
+  for (const gp_tuning &t : space) {
+    gp_status rc = consider(t);
+    if (rc) return rc;
   }
-  if (g->kind == GP_PIP) {
-    // then the vertex-parallel threshold, on the best configuration
-    for (int vp : {-1, 4, 8, 32, 64}) {
+  {
+    // then the vertex-parallel threshold, on the best configuration (P2P: one-wave items)
+    for (int vp : {-1, 4, 8, 16, 32, 64}) {
+      if (vp == best_cfg.vp_points || (g->kind == GP_P2P && best_cfg.waves_per_item != 1))
+        continue;
       gp_tuning t = best_cfg;
       t.vp_points = vp;
-      float times[3];
-      for (int r = 0; r < 4; ++r) {
-        gp_stats st;
-        gp_status rc = run_query(g, g->kind, n, px, py, d_id.as<int32_t>(), d_dist.as<double>(),
-                                 prec, ws, ws_bytes, s, &st, &t);
-        if (rc) return rc;
-        if (r > 0) times[r - 1] = st.ms_total;
-      }
-      std::sort(times, times + 3);
-      if (times[1] < best_t) {
-        best_t = times[1];
-        best_cfg = t;
-      }
+      gp_status rc = consider(t);
+      if (rc) return rc;
     }
   }
   g->tune[prec] = best_cfg;

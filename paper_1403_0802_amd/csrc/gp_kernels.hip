@@ -1726,8 +1726,82 @@ __device__ void pipmix_pre_item(const RefineArgs &a, const Item it, float4 *lds)
 // than the chunk continues in the next one).  tab[q] = (fid, end slot | continues<<31).
 
 struct alignas(16) SegRec64 {
-  double ax, ay, bx, by, dx, dy, L2, pad;
+  double ax, ay, bx, by, dx, dy, L2, L2p;
 };
+
+// ------------------------------------------------------------------------- P2P, vertex-parallel
+
+__device__ __forceinline__ double wave_min_f64(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, GP_WAVE));
+  return v;
+}
+
+__device__ __forceinline__ double lane_double(double v, int p) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), p),
+                          __builtin_amdgcn_readlane(__double2loint(v), p));
+}
+
+// Vertex-parallel refinement of a P2P item with few points (the alternative mapping of
+// Sec. III.B, with the cross-lane minimum): lanes take the segments of a candidate
+// polyline, the wave loops over the item's points (lane p holds point p and its result),
+// and a polyline's distance to point p is the exact minimum over the lanes.  FP64 with the
+// definition's operation order; a perpendicular quotient is divided out only when it could
+// still beat min(best, next(D*D)) (cc >= fl(thr*L2)*(1+2^-49) implies cc/L2 > thr), so
+// the results are the definition's in both precision forms.
+__device__ void p2p_vp_item(const RefineArgs &a, const Item it) {
+  const uint32_t lane = lane_id();
+  const int np = it.npts;  // <= a.vp_points <= 64
+  double qx = 0.0, qy = 0.0;
+  if ((int)lane < np) {
+    const double2 p = a.xy[it.pt_lo + (int)lane];
+    qx = p.x;
+    qy = p.y;
+  }
+  double best = a.D2_next;  // accept d2 <= fl(D*D); later only strictly smaller
+  int32_t bid = -1;
+  const int32_t k0 = a.cand_off[it.cell], k1 = a.cand_off[it.cell + 1];
+  for (int32_t k = k0; k < k1; ++k) {
+    const int32_t f = a.cand_id[k];
+    const int32_t s0 = a.eoff[f], s1 = a.eoff[f + 1];
+    for (int p = 0; p < np; ++p) {
+      const double px = lane_double(qx, p), py = lane_double(qy, p);
+      const double thr = lane_double(best, p);
+      double dmin = INFINITY;
+      for (int32_t e0 = s0; e0 < s1; e0 += GP_WAVE) {
+        const int32_t e = e0 + (int32_t)lane;
+        if (e < s1) {
+          const double4 r = a.edge64[e];
+          const double dx = r.z - r.x, dy = r.w - r.y;
+          const double wx = px - r.x, wy = py - r.y;
+          const double L2 = dx * dx + dy * dy;
+          const double t = wx * dx + wy * dy;
+          double d2;
+          if (t <= 0.0) {
+            d2 = wx * wx + wy * wy;
+          } else if (t >= L2) {
+            const double ex = px - r.z, ey = py - r.w;
+            d2 = ex * ex + ey * ey;
+          } else {
+            const double c = wx * dy - wy * dx;
+            const double cc = c * c;
+            d2 = cc < (thr * L2) * (1.0 + 0x1p-49) ? cc / L2 : INFINITY;
+          }
+          dmin = fmin(dmin, d2);
+        }
+      }
+      dmin = wave_min_f64(dmin);
+      if ((int)lane == p && dmin < best) {
+        best = dmin;
+        bid = f;
+      }
+    }
+  }
+  if ((int)lane < np) {
+    const uint32_t o = a.perm[it.pt_lo + (int)lane];
+    a.out_id[o] = bid;
+    a.out_dist[o] = bid >= 0 ? sqrt(best) : INFINITY;
+  }
+}
 
 // ------------------------------------------------------------------------- P2P, FP64
 // P2P work items may span W wavefronts (W*64*PPL points) that share one LDS staging of
@@ -1748,6 +1822,10 @@ __device__ __forceinline__ void load_points64w(const RefineArgs &a, const Item i
 
 template <int PPL, int W>
 __device__ void p2p64_item(const RefineArgs &a, const Item it, SegRec64 *lds, int2 *tab) {
+  if (W == 1 && it.npts <= a.vp_points) {
+    p2p_vp_item(a, it);
+    return;
+  }
   const int tid = (int)threadIdx.x;
   const int wbase = (int)(threadIdx.x / GP_WAVE) * GP_WAVE * PPL;
   const bool wave_live = wbase < it.npts;
@@ -1777,7 +1855,9 @@ __device__ void p2p64_item(const RefineArgs &a, const Item it, SegRec64 *lds, in
         q.dx = r.z - r.x;
         q.dy = r.w - r.y;
         q.L2 = q.dx * q.dx + q.dy * q.dy;
-        q.pad = 0.0;
+        // fl(L2 (1 + 2^-48)): best * L2p >= best * L2 (1 + 2^-49) after rounding, the
+        // bound that decides whether a perpendicular quotient can still win
+        q.L2p = q.L2 * (1.0 + 0x1p-48);
         lds[filled + t] = q;
       }
       filled += take;
@@ -1794,27 +1874,42 @@ __device__ void p2p64_item(const RefineArgs &a, const Item it, SegRec64 *lds, in
       const int2 te = tab[q];
       const int32_t f = te.x;
       const int end = te.y & 0x7fffffff;
+      // The slots of one table entry are consecutive segments of polyline f, so the b
+      // endpoint of slot t is the a endpoint of slot t + 1: its difference to the point
+      // and squared distance are computed once and carried (bitwise the same values the
+      // definition computes for both segments).
+      double wx[PPL], wy[PPL], da[PPL];
+      if (start < end) {
+        const double ax = lds[start].ax, ay = lds[start].ay;
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+          wx[j] = px[j] - ax;
+          wy[j] = py[j] - ay;
+          da[j] = wx[j] * wx[j] + wy[j] * wy[j];
+        }
+      }
       for (int t = start; t < end; ++t) {
         const SegRec64 r = lds[t];
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-          const double wx = px[j] - r.ax, wy = py[j] - r.ay;
-          const double tt = wx * r.dx + wy * r.dy;
-          const double da = wx * wx + wy * wy;
+          const double tt = wx[j] * r.dx + wy[j] * r.dy;
           const double ex = px[j] - r.bx, ey = py[j] - r.by;
           const double db = ex * ex + ey * ey;
-          const double c = wx * r.dy - wy * r.dx;
+          const double c = wx[j] * r.dy - wy[j] * r.dx;
           const double cc = c * c;
           const bool ca = tt <= 0.0;
           const bool cb = !ca & (tt >= r.L2);
-          double d2 = ca ? da : db;
+          double d2 = ca ? da[j] : db;
           const bool cp = !ca & !cb;
-          // The perpendicular case divides only when its quotient could still beat
-          // the current best: cc >= fl(best*L2)*(1+2^-49) implies cc/L2 > best.
-          const double lim = (best[j] * r.L2) * (1.0 + 0x1p-49);
+          // The perpendicular case divides only when its quotient could still beat the
+          // current best: cc >= fl(best * L2p) >= fl(best*L2)*(1+2^-49) implies
+          // cc/L2 > best.
           d2 = cp ? INFINITY : d2;
-          if (cp && cc < lim) d2 = cc / r.L2;
+          if (cp && cc < best[j] * r.L2p) d2 = cc / r.L2;
           if (d2 < best[j]) { best[j] = d2; bid[j] = f; }
+          wx[j] = ex;
+          wy[j] = ey;
+          da[j] = db;
         }
       }
       start = end;
@@ -2453,7 +2548,9 @@ __device__ __forceinline__ void p2pmix_loop(const RefineArgs &a, int persistent)
     // runs with the fewest points per lane that hold them, so its idle point slots cost
     // no tests.
     const Item item = a.items[it];
-    if (W == 1 && PPL >= 4 && item.npts <= 128 && item.npts > 64)
+    if (W == 1 && item.npts <= a.vp_points)
+      p2p_vp_item(a, item);  // FP64, final in both forms
+    else if (W == 1 && PPL >= 4 && item.npts <= 128 && item.npts > 64)
       p2pmix_item<2, W, PRE>(a, item, U, V, tab, slotseg, slotf, red, smem);
     else if (W == 1 && PPL >= 2 && item.npts <= 64)
       p2pmix_item<1, W, PRE>(a, item, U, V, tab, slotseg, slotf, red, smem);
@@ -2551,11 +2648,6 @@ hipError_t launch_refine(gp_kind kind, gp_precision prec, const RefineArgs &a,
 // the definitions' operation order, straight from the edge records.  Threads take the
 // edges of a feature; parity combines by counting odd threads (XOR), distance by an
 // exact wave minimum -- both independent of order.
-
-__device__ __forceinline__ double wave_min_f64(double v) {
-  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, GP_WAVE));
-  return v;
-}
 
 // PIP: one workgroup per queued point.  Its threads split each candidate polygon's
 // edges; the polygon's parity is that of the number of threads with an odd count of

@@ -118,6 +118,10 @@ _SIGS = {
     "gp_autotune": ([_P, c_int32, c_int64, _P, _P, _P, ctypes.c_size_t, _P, POINTER(gp_tuning),
                      POINTER(c_float)], c_int32),
     "gp_probe_rate": ([c_int32, c_int32, POINTER(c_double), POINTER(c_float)], c_int32),
+    "gp_tuning_cache_save": ([c_char_p], c_int32),
+    "gp_tuning_cache_load": ([c_char_p], c_int32),
+    "gp_tuning_cache_clear": ([], c_int32),
+    "gp_tuning_cache_size": ([POINTER(c_int64)], c_int32),
     "gp_sweep_cell_size": ([c_int32, _P, _P, _P, c_int32, c_int64, _P, _P, c_int32, _P,
                             POINTER(c_double), _P, _P, _P, _P], c_int32),
     "gp_serve_create": ([_P, _P, POINTER(gp_serve_opts), POINTER(_P)], c_int32),
@@ -279,6 +283,24 @@ def gp_autotune(grid, prec, px, py, ws, stream=None):
                           _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(t),
                           ctypes.byref(ms)))
     return t.as_dict(), ms.value
+
+
+def gp_tuning_cache_save(path):
+    check(lib.gp_tuning_cache_save(os.fsencode(path)))
+
+
+def gp_tuning_cache_load(path):
+    check(lib.gp_tuning_cache_load(os.fsencode(path)))
+
+
+def gp_tuning_cache_clear():
+    check(lib.gp_tuning_cache_clear())
+
+
+def gp_tuning_cache_size() -> int:
+    n = c_int64()
+    check(lib.gp_tuning_cache_size(ctypes.byref(n)))
+    return n.value
 
 
 # --------------------------------------------------------------------------- convenience

@@ -160,7 +160,7 @@ def test_golden_fixtures(gp, name, prec):
     c = golden_cases.load(name)
     for cs, pre in ((1.0, 0), (2.5, 0), (1.0, 1), (2.5, 1)):
         for tuning in (None, dict(points_per_lane=2, vp_points=-1),
-                       dict(points_per_lane=4, vp_points=-1)):
+                       dict(points_per_lane=4, vp_points=-1), dict(points_per_lane=1, vp_points=64)):
             say("golden", name, prec, cs, "prestage", pre, tuning)
             grid = gp.gp_build_grid(c.kind, c.geom, synth.GridParams(cell_size=cs,
                                                                      radius_D=c.radius,
@@ -178,11 +178,16 @@ def test_golden_fixtures(gp, name, prec):
 
 TUNINGS = [dict(points_per_lane=p, edge_chunk=e, wg_per_cu=wg, persistent=pe)
            for p in (1, 2, 4) for e in (64, 256, 512) for wg, pe in ((8, 1), (2, 1), (8, 0))]
-# P2P work items may also span 2 or 4 wavefronts sharing one LDS staging
+# P2P work items may also span 2 or 4 wavefronts sharing one LDS staging, and one-wave
+# items with few points may go vertex-parallel (lanes over segments)
 TUNINGS_P2P = TUNINGS + [dict(points_per_lane=p, edge_chunk=e, wg_per_cu=wg, persistent=pe,
                               waves_per_item=wv)
                          for wv in (2, 4) for p in (1, 4) for e in (64, 512)
-                         for wg, pe in ((4, 1), (8, 0))]
+                         for wg, pe in ((4, 1), (8, 0))] + [
+                         dict(points_per_lane=p, edge_chunk=128, wg_per_cu=8, persistent=pe,
+                              vp_points=vp, waves_per_item=wv)
+                         for vp in (1, 5, 16, 64) for p in (1, 4) for pe in (0, 1)
+                         for wv in (1, 2)]
 # PIP items with few points may go vertex-parallel (lanes over edges): never, always
 # (64), and thresholds in between, with both point-parallel shapes around them
 TUNINGS_PIP = TUNINGS + [dict(points_per_lane=p, edge_chunk=128, wg_per_cu=8, persistent=pe,

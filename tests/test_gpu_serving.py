@@ -232,13 +232,33 @@ def test_errors(setup):
     assert gp.lib.gp_serve_destroy(None) == gp.GP_E_INVALID_ARG
 
 
-def test_autotune_keeps_results(setup):
+def test_autotune_keeps_results(setup, tmp_path):
+    """The autotuner's winner gives the oracle's results; a second call on the same
+    workload class takes the cached winner without the search; the cache survives a save,
+    clear and load."""
+    import time
     gp, g3, g4, reqs, want = setup
     kind, x, y = reqs[0]
     ws = gp.new_workspace(g3, x.numel(), "mixed")
+    gp.gp_tuning_cache_clear()
+    t0 = time.perf_counter()
     best, ms = gp.gp_autotune(g3, "mixed", x, y, ws)
+    t_search = time.perf_counter() - t0
     assert best["points_per_lane"] in (1, 2, 4) and ms > 0
     assert gp.gp_get_tuning(g3, "mixed") == best
+    assert gp.gp_tuning_cache_size() == 1
+    gp.gp_reset_tuning(g3, "mixed")
+    path = str(tmp_path / "tune.txt")
+    gp.gp_tuning_cache_save(path)
+    gp.gp_tuning_cache_clear()
+    gp.gp_tuning_cache_load(path)
+    t0 = time.perf_counter()
+    best2, _ = gp.gp_autotune(g3, "mixed", x, y, ws)
+    t_hit = time.perf_counter() - t0
+    assert best2 == best and gp.gp_get_tuning(g3, "mixed") == best
+    assert gp.gp_tuning_cache_size() == 1
+    assert t_hit < t_search / 3, (t_hit, t_search)
+    gp.gp_tuning_cache_clear()
     r = gp.run(g3, x, y, "mixed")
     assert torch.equal(r.cpu(), want[0][0])
     gp.gp_reset_tuning(g3, "mixed")
