@@ -311,7 +311,7 @@ def cell_sweep(gp, torch, dev, c3, c4, which="both"):
     point sets, mixed form, default kernel tuning; `which` is "pip", "p2p" or "both"."""
     out = {}
     for name, kind, (geom, p, px, py), sizes in (
-            ("pip_c3", "pip", c3, [1 / 256, 1 / 512, 1 / 1024, 1 / 2048, 1 / 4096]),
+            ("pip_c3", "pip", c3, [1 / 128, 1 / 256, 1 / 512, 1 / 1024, 1 / 2048]),
             ("p2p_c4", "p2p", c4, [25.0, 50.0, 100.0, 200.0, 400.0])):
         if which not in ("both", kind):
             continue

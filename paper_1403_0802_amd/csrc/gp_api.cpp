@@ -641,6 +641,7 @@ size_t workspace_layout(const Grid &g, int64_t n, gp_precision prec, void *base,
     w.ikA = w.ikB = w.ivA = w.ivB = nullptr;
     w.items_sorted = nullptr;
   }
+  w.vp_list = g.kind == GP_P2P ? (uint32_t *)take(mi * 4) : nullptr;
   w.counters = (uint32_t *)take(C_COUNT * 4);
   w.tests = (unsigned long long *)take(16);
   w.xyA = (double2 *)take(un * 16);
@@ -767,6 +768,8 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   a.rq_count = w.counters + C_RQ;
   a.edge_chunk = t.edge_chunk;
   a.vp_points = t.vp_points;
+  a.vp_list = w.vp_list;
+  a.vp_count = w.counters + C_NVP;
 
   GP_TRY_HIP(launch_unpaired(a, n, w.counters + C_NPAIRED, s));
   GP_TRY_HIP(launch_items(w.pt_off, g->d_cand_off, segf ? g->d_cell_segs : g->d_cell_edges,

@@ -70,7 +70,9 @@ struct RefineArgs {
   uint32_t *rq;
   uint32_t *rq_count;
   int32_t edge_chunk;
-  int32_t vp_points;         // PIP: items with at most this many points go vertex-parallel
+  int32_t vp_points;         // items with at most this many points go vertex-parallel
+  uint32_t *vp_list;         // P2P mixed: indices of those items, collected before the
+  uint32_t *vp_count;        //   refinement (count zeroed with the counters)
 };
 
 // Device-resident grid.
@@ -123,6 +125,7 @@ struct Workspace {
   Item *items;
   uint32_t *ikA, *ikB, *ivA, *ivB;  // PIP: sort of the items by cost (max_items each)
   Item *items_sorted;
+  uint32_t *vp_list;     // P2P: the vertex-parallel items (max_items)
   uint32_t *rq;
   uint32_t *counters;    // [16]: 0 item counter, 1 rq count, 2 n_items(copy), ...
   unsigned long long *tests;  // [1]
@@ -130,7 +133,7 @@ struct Workspace {
 };
 
 // C_ITEM .. C_ITEM + GP_XCDS - 1: the item queues of the persistent launches, one per XCD.
-enum Counter { C_RQ = 1, C_NITEMS = 2, C_NPAIRED = 3, C_ITEM = 8, C_COUNT = 16 };
+enum Counter { C_RQ = 1, C_NITEMS = 2, C_NPAIRED = 3, C_NVP = 4, C_ITEM = 8, C_COUNT = 16 };
 
 size_t workspace_layout(const Grid &g, int64_t n, gp_precision prec, void *base, Workspace *ws);
 size_t scan_tmp_elems(size_t n);

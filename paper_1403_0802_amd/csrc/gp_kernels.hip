@@ -1736,70 +1736,89 @@ __device__ __forceinline__ double wave_min_f64(double v) {
   return v;
 }
 
-__device__ __forceinline__ double lane_double(double v, int p) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), p),
-                          __builtin_amdgcn_readlane(__double2loint(v), p));
+__device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, GP_WAVE));
+  return v;
 }
 
 // Vertex-parallel refinement of a P2P item with few points (the alternative mapping of
-// Sec. III.B, with the cross-lane minimum): lanes take the segments of a candidate
-// polyline, the wave loops over the item's points (lane p holds point p and its result),
-// and a polyline's distance to point p is the exact minimum over the lanes.  FP64 with the
-// definition's operation order; a perpendicular quotient is divided out only when it could
-// still beat min(best, next(D*D)) (cc >= fl(thr*L2)*(1+2^-49) implies cc/L2 > thr), so
-// the results are the definition's in both precision forms.
+// Sec. III.B, with the cross-lane minimum): lanes take the segments of the cell's
+// candidate polylines, four of the item's points at a time.  Each lane keeps, per point,
+// the smallest distance it has seen within range and the polyline it came from (the
+// candidates ascend by id, so a later equal distance keeps the smaller id); the point's
+// answer is the smallest (distance, id) pair over the lanes, which is the nearest
+// polyline in range with ties to the smaller id.  FP64 in the definition's operation
+// order; a perpendicular quotient is divided out only when it could still beat the
+// lane's best, itself at most next(D*D) (cc >= fl(thr*L2)*(1+2^-49) implies
+// cc/L2 > thr), so the results are the definition's in both precision forms.  No lane
+// waits on another inside the loops: candidate ids and segment ranges arrive 64 at a
+// time in one round trip, and the only cross-lane steps are the final minima.
 __device__ void p2p_vp_item(const RefineArgs &a, const Item it) {
   const uint32_t lane = lane_id();
-  const int np = it.npts;  // <= a.vp_points <= 64
-  double qx = 0.0, qy = 0.0;
-  if ((int)lane < np) {
-    const double2 p = a.xy[it.pt_lo + (int)lane];
-    qx = p.x;
-    qy = p.y;
-  }
-  double best = a.D2_next;  // accept d2 <= fl(D*D); later only strictly smaller
-  int32_t bid = -1;
+  const int np = it.npts;  // 1 .. a.vp_points (<= 64)
   const int32_t k0 = a.cand_off[it.cell], k1 = a.cand_off[it.cell + 1];
-  for (int32_t k = k0; k < k1; ++k) {
-    const int32_t f = a.cand_id[k];
-    const int32_t s0 = a.eoff[f], s1 = a.eoff[f + 1];
-    for (int p = 0; p < np; ++p) {
-      const double px = lane_double(qx, p), py = lane_double(qy, p);
-      const double thr = lane_double(best, p);
-      double dmin = INFINITY;
-      for (int32_t e0 = s0; e0 < s1; e0 += GP_WAVE) {
-        const int32_t e = e0 + (int32_t)lane;
-        if (e < s1) {
+  for (int g = 0; g < np; g += 4) {
+    double px[4], py[4], best[4];
+    int32_t bid[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double2 p = a.xy[it.pt_lo + min(g + j, np - 1)];
+      px[j] = p.x;
+      py[j] = p.y;
+      best[j] = a.D2_next;  // accept d2 <= fl(D*D); later only strictly smaller
+      bid[j] = -1;
+    }
+    for (int32_t kw = k0; kw < k1; kw += GP_WAVE) {
+      const int32_t kk = kw + (int32_t)lane;
+      int32_t wf = 0, w0 = 0, w1 = 0;
+      if (kk < k1) {
+        wf = a.cand_id[kk];
+        w0 = a.eoff[wf];
+        w1 = a.eoff[wf + 1];
+      }
+      const int nk = min(GP_WAVE, k1 - kw);
+      for (int q = 0; q < nk; ++q) {
+        const int32_t f = __builtin_amdgcn_readlane(wf, q);
+        const int32_t s1 = __builtin_amdgcn_readlane(w1, q);
+#pragma unroll 1
+        for (int32_t e = __builtin_amdgcn_readlane(w0, q) + (int32_t)lane; e < s1;
+             e += GP_WAVE) {
           const double4 r = a.edge64[e];
           const double dx = r.z - r.x, dy = r.w - r.y;
-          const double wx = px - r.x, wy = py - r.y;
           const double L2 = dx * dx + dy * dy;
-          const double t = wx * dx + wy * dy;
-          double d2;
-          if (t <= 0.0) {
-            d2 = wx * wx + wy * wy;
-          } else if (t >= L2) {
-            const double ex = px - r.z, ey = py - r.w;
-            d2 = ex * ex + ey * ey;
-          } else {
-            const double c = wx * dy - wy * dx;
-            const double cc = c * c;
-            d2 = cc < (thr * L2) * (1.0 + 0x1p-49) ? cc / L2 : INFINITY;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const double wx = px[j] - r.x, wy = py[j] - r.y;
+            const double t = wx * dx + wy * dy;
+            double d2;
+            if (t <= 0.0) {
+              d2 = wx * wx + wy * wy;
+            } else if (t >= L2) {
+              const double ex = px[j] - r.z, ey = py[j] - r.w;
+              d2 = ex * ex + ey * ey;
+            } else {
+              const double c = wx * dy - wy * dx;
+              const double cc = c * c;
+              d2 = cc < (best[j] * L2) * (1.0 + 0x1p-49) ? cc / L2 : INFINITY;
+            }
+            if (d2 < best[j]) {
+              best[j] = d2;
+              bid[j] = f;
+            }
           }
-          dmin = fmin(dmin, d2);
         }
       }
-      dmin = wave_min_f64(dmin);
-      if ((int)lane == p && dmin < best) {
-        best = dmin;
-        bid = f;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double m = wave_min_f64(best[j]);
+      const int32_t b = wave_min_i32(best[j] == m && bid[j] >= 0 ? bid[j] : INT32_MAX);
+      if (lane == 0 && g + j < np) {
+        const uint32_t o = a.perm[it.pt_lo + g + j];
+        a.out_id[o] = b == INT32_MAX ? -1 : b;
+        a.out_dist[o] = b == INT32_MAX ? INFINITY : sqrt(m);
       }
     }
-  }
-  if ((int)lane < np) {
-    const uint32_t o = a.perm[it.pt_lo + (int)lane];
-    a.out_id[o] = bid;
-    a.out_dist[o] = bid >= 0 ? sqrt(best) : INFINITY;
   }
 }
 
@@ -1822,10 +1841,7 @@ __device__ __forceinline__ void load_points64w(const RefineArgs &a, const Item i
 
 template <int PPL, int W>
 __device__ void p2p64_item(const RefineArgs &a, const Item it, SegRec64 *lds, int2 *tab) {
-  if (W == 1 && it.npts <= a.vp_points) {
-    p2p_vp_item(a, it);
-    return;
-  }
+  if (W == 1 && it.npts <= a.vp_points) return;  // refined by k_p2p_vp
   const int tid = (int)threadIdx.x;
   const int wbase = (int)(threadIdx.x / GP_WAVE) * GP_WAVE * PPL;
   const bool wave_live = wbase < it.npts;
@@ -2548,9 +2564,9 @@ __device__ __forceinline__ void p2pmix_loop(const RefineArgs &a, int persistent)
     // runs with the fewest points per lane that hold them, so its idle point slots cost
     // no tests.
     const Item item = a.items[it];
-    if (W == 1 && item.npts <= a.vp_points)
-      p2p_vp_item(a, item);  // FP64, final in both forms
-    else if (W == 1 && PPL >= 4 && item.npts <= 128 && item.npts > 64)
+    if (W == 1 && item.npts <= a.vp_points) {
+      // refined by k_p2p_vp
+    } else if (W == 1 && PPL >= 4 && item.npts <= 128 && item.npts > 64)
       p2pmix_item<2, W, PRE>(a, item, U, V, tab, slotseg, slotf, red, smem);
     else if (W == 1 && PPL >= 2 && item.npts <= 64)
       p2pmix_item<1, W, PRE>(a, item, U, V, tab, slotseg, slotf, red, smem);
@@ -2559,6 +2575,32 @@ __device__ __forceinline__ void p2pmix_loop(const RefineArgs &a, int persistent)
     if (!persistent) break;
     it = W == 1 ? next_item(a, n_items) : next_item_wg(a, n_items, &s_item);
   }
+}
+
+// P2P's vertex-parallel items (at most vp_points points) run in a kernel of their own,
+// in both precision forms (inlined into the refinement loops, their code would cost those
+// loops registers and with them resident waves): k_vp_collect lists them (one atomic per
+// wave), k_p2p_vp gives each a wave.
+__global__ __launch_bounds__(256) void k_vp_collect(RefineArgs a) {
+  const uint32_t n_items = *a.n_items;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n_items; base += gridDim.x * blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    const bool vp = i < n_items && a.items[i].npts <= a.vp_points;
+    const uint64_t m = ballot(vp);
+    if (m == 0) continue;
+    uint32_t first = 0;
+    if (lane_id() == 0) first = atomicAdd(a.vp_count, (uint32_t)__popcll(m));
+    first = (uint32_t)__builtin_amdgcn_readfirstlane((int)first);
+    if (vp) a.vp_list[first + (uint32_t)__popcll(m & lanemask_lt())] = i;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_p2p_vp(RefineArgs a) {
+  const uint32_t nvp = *a.vp_count;
+  const uint32_t waves = gridDim.x * (blockDim.x / GP_WAVE);
+  for (uint32_t q = blockIdx.x * (blockDim.x / GP_WAVE) + threadIdx.x / GP_WAVE; q < nvp;
+       q += waves)
+    p2p_vp_item(a, a.items[a.vp_list[q]]);
 }
 
 template <int PPL, int W>
@@ -2634,12 +2676,19 @@ hipError_t launch_refine(gp_kind kind, gp_precision prec, const RefineArgs &a,
     GP_DISPATCH(k_pipmix_pre, ppl, dim3(grid), blk, lds, s, a, pers);
   else if (kind == GP_PIP)
     GP_DISPATCH(k_pipmix, ppl, dim3(grid), blk, lds, s, a, pers);
-  else if (prec == GP_FP64)
-    GP_DISPATCH_W(k_p2p64, ppl, W, dim3(grid), blk, lds, s, a, pers);
-  else if (a.recU)
-    GP_DISPATCH_W(k_p2pmix_pre, ppl, W, dim3(grid), blk, lds, s, a, pers);
-  else
-    GP_DISPATCH_W(k_p2pmix, ppl, W, dim3(grid), blk, lds, s, a, pers);
+  else {
+    if (W == 1 && t.vp_points > 0) {
+      const unsigned gc = (unsigned)std::min<int64_t>((max_items + 255) / 256, 4096);
+      hipLaunchKernelGGL(k_vp_collect, dim3(gc < 1 ? 1 : gc), dim3(256), 0, s, a);
+      hipLaunchKernelGGL(k_p2p_vp, dim3((unsigned)num_cu * 8), dim3(256), 0, s, a);
+    }
+    if (prec == GP_FP64)
+      GP_DISPATCH_W(k_p2p64, ppl, W, dim3(grid), blk, lds, s, a, pers);
+    else if (a.recU)
+      GP_DISPATCH_W(k_p2pmix_pre, ppl, W, dim3(grid), blk, lds, s, a, pers);
+    else
+      GP_DISPATCH_W(k_p2pmix, ppl, W, dim3(grid), blk, lds, s, a, pers);
+  }
   return hipGetLastError();
 }
 
