@@ -496,10 +496,14 @@ def main():
     for key, which, iters in (("fp32_fma_vgpr_tflops", 0, 20000), ("fp32_fma_sgpr_tflops", 4, 20000),
                               ("fp64_fma_tflops", 1, 10000),
                               ("p2p_test_sgpr_consts_tests_per_s", 3, 5000),
-                              ("p2p_test_vgpr_tests_per_s", 5, 20000)):
+                              ("p2p_test_vgpr_tests_per_s", 5, 20000),
+                              ("pip_test_vgpr_2x8_tests_per_s", 6, 5000),
+                              ("pip_test_vgpr_4x4_tests_per_s", 7, 5000)):
         r, _ = gp.gp_probe_rate(which, iters)
         probes[key] = r / 1e12 if key.endswith("tflops") else r
     probes["p2p_refine_vs_vgpr_probe"] = (tests_p2p / (p2p_ref / 1e3)) / probes["p2p_test_vgpr_tests_per_s"]
+    probes["pip_refine_vs_vgpr_probe"] = (tests_pip / (pip_ref / 1e3)) / max(
+        probes["pip_test_vgpr_2x8_tests_per_s"], probes["pip_test_vgpr_4x4_tests_per_s"])
     detail["probes"] = probes
     # PIP with cell classes (Sec. III.A): points in cells wholly inside a polygon take its
     # id untested, cells outside are skipped; same ids, fewer tests (reported apart from

@@ -146,7 +146,8 @@ typedef struct gp_tuning {
     int32_t vp_points;       /* items with at most this many points (1..64) use the
                                 vertex-parallel mapping (lanes over edges or segments, the
                                 wave looping over the points; FP64, Sec. III.B's
-                                alternative; P2P: one-wave items only); -1 never;
+                                alternative; P2P: one-wave items only, refined by a
+                                kernel of their own ahead of the others); -1 never;
                                 0 = library default (PIP 16, P2P 4) */
 } gp_tuning;
 
@@ -274,7 +275,9 @@ gp_status gp_sweep_cell_size(gp_kind kind, const gp_geometry *geom, const gp_gri
  * 2: LDS broadcast 16-byte reads (wave reads/s), 3: the mixed P2P point-segment test on
  * register data with the segment constants in SGPRs (tests/s), 4: FP32 FMA with one
  * SGPR operand (FLOP/s), 5: the mixed P2P test on per-lane VGPR data, four points
- * against two segments per step (tests/s).  `iters` sets the
+ * against two segments per step (tests/s), 6 and 7: the mixed PIP crossing test on
+ * per-lane VGPR data, two points per lane against eight edges per step and four against
+ * four (tests/s).  `iters` sets the
  * loop length; *ms receives the kernel time.  Synchronous; GP_E_INVALID_ARG for other
  * `which` or iters <= 0. */
 gp_status gp_probe_rate(int32_t which, int32_t iters, double *rate, float *ms);
