@@ -36,6 +36,7 @@ namespace gp {
 #define RS_TILE (RS_THREADS * RS_ITEMS)
 #define RS_MAX_BITS 8
 #define RS_MAX_BUCKETS (1 << RS_MAX_BITS)
+static_assert(RS_THREADS == SCAN_THREADS, "the tile scan uses the block scan");
 
 __device__ __forceinline__ uint64_t ballot(bool c) { return __builtin_amdgcn_ballot_w64(c); }
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -209,29 +210,39 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t *keys, si
 // Payload: pass 0 reads it from the caller's separate x/y arrays (px0, py0), later
 // passes from the interleaved array pin; it is written interleaved to pout.
 //
-// Each tile is first sorted by digit in LDS (stable: records are ranked in input order,
-// round by round, wave by wave, lane by lane, with ballot peer masks), then written out
-// in that order, so consecutive threads store consecutive records of one digit: the
-// global writes form runs instead of single scattered records.
+// Each tile is first sorted by digit in LDS, then written out in that order, so
+// consecutive threads store consecutive records of one digit: the global writes form runs
+// instead of single scattered records.  The order is stable: a record's rank among equal
+// digits comes from ballot peer masks within its wave, and the waves' per-digit counts,
+// kept for every round of the tile, are turned into offsets in record order (round, then
+// wave, then lane) by one pass per digit -- five barriers per tile.
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, size_t n,
     int shift, int bits, const uint32_t *offs, uint32_t nblk, const double *px0,
     const double *py0, const double2 *pin, double2 *pout) {
-  __shared__ uint32_t sk[RS_TILE], sv[RS_TILE];
-  __shared__ double2 sp[RS_TILE];
-  __shared__ uint32_t lpos[RS_MAX_BUCKETS];  // histogram, then next free local slot
-  __shared__ uint32_t delta[RS_MAX_BUCKETS]; // global start - local start of each digit
-  __shared__ uint8_t wcnt[RS_THREADS / GP_WAVE][RS_MAX_BUCKETS];
+  constexpr int NW = RS_THREADS / GP_WAVE;
+  // the per-(round, wave, digit) counts, then offsets, share LDS with the sorted tile
+  __shared__ union {
+    struct {
+      uint32_t k[RS_TILE], v[RS_TILE];
+      double2 p[RS_TILE];
+    } t;
+    uint16_t wo[RS_ITEMS * NW * RS_MAX_BUCKETS];
+  } sm;
+  __shared__ uint32_t lpos[RS_MAX_BUCKETS];   // local start of each digit
+  __shared__ uint32_t delta[RS_MAX_BUCKETS];  // global start - local start of each digit
   const uint32_t tid = threadIdx.x, wave = tid / GP_WAVE;
   const uint32_t nb = 1u << bits, mask = nb - 1u;
-  const size_t base = (size_t)blockIdx.x * RS_TILE;
+  // Workgroup b runs on XCD b mod 8; each XCD takes a contiguous range of tiles, so the
+  // runs that neighbouring tiles write for one digit (adjacent in the output, sharing
+  // cache lines at their ends) are merged in one L2.  The grid covers 8 ranges of
+  // ceil(nblk / 8) tiles; the few workgroups past the last tile exit.
+  const uint32_t per = (nblk + GP_XCDS - 1) / GP_XCDS;
+  const uint32_t tile = (blockIdx.x % GP_XCDS) * per + blockIdx.x / GP_XCDS;
+  if (tile >= nblk) return;
+  const size_t base = (size_t)tile * RS_TILE;
   const int tn = (int)((n - base) < (size_t)RS_TILE ? (n - base) : (size_t)RS_TILE);
-  for (uint32_t d = tid; d < RS_MAX_BUCKETS; d += RS_THREADS) {
-    lpos[d] = 0;
-    for (int w = 0; w < RS_THREADS / GP_WAVE; ++w) wcnt[w][d] = 0;
-  }
-  __syncthreads();
-  // the tile's records, in registers; local digit histogram
+  // the tile's records, in registers
   uint32_t k[RS_ITEMS], v[RS_ITEMS];
   double2 pl[RS_ITEMS];
 #pragma unroll
@@ -243,32 +254,13 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     v[r] = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
     pl[r] = make_double2(0.0, 0.0);
     if (valid && pout) pl[r] = pin ? pin[i] : make_double2(px0[i], py0[i]);
-    if (valid) atomicAdd(&lpos[(k[r] >> shift) & mask], 1u);
   }
+  for (uint32_t j = tid; j < RS_ITEMS * NW * RS_MAX_BUCKETS / 2; j += RS_THREADS)
+    ((uint32_t *)sm.wo)[j] = 0u;
   __syncthreads();
-  // exclusive scan of the histogram: thread t owns digits 4t .. 4t+3
-  {
-    uint32_t c[4], sum = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t d = 4 * tid + q;
-      c[q] = d < nb ? lpos[d] : 0u;
-      sum += c[q];
-    }
-    uint32_t tot;
-    uint32_t pre = block_excl_scan(sum, &tot);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t d = 4 * tid + q;
-      if (d < nb) {
-        lpos[d] = pre;
-        delta[d] = offs[(size_t)d * nblk + blockIdx.x] - pre;
-      }
-      pre += c[q];
-    }
-  }
-  __syncthreads();
-  // stable ranking into LDS
+  // rank of every record among the equal digits of its wave and round; the first such
+  // lane records their count
+  uint32_t rank[RS_ITEMS];
 #pragma unroll
   for (int r = 0; r < RS_ITEMS; ++r) {
     const bool valid = r * RS_THREADS + (int)tid < tn;
@@ -278,34 +270,53 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
       const uint64_t m = ballot((d >> b) & 1u);
       peers &= ((d >> b) & 1u) ? m : ~m;
     }
-    const uint32_t rank = __popcll(peers & lanemask_lt());
-    if (valid && rank == 0) wcnt[wave][d] = (uint8_t)__popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = lpos[d] + rank;
-      for (uint32_t w = 0; w < wave; ++w) pos += wcnt[w][d];
-      sk[pos] = k[r];
-      sv[pos] = v[r];
-      if (pout) sp[pos] = pl[r];
-    }
-    __syncthreads();
-    for (uint32_t dd = tid; dd < nb; dd += RS_THREADS) {
-      uint32_t add = 0;
-      for (int w = 0; w < RS_THREADS / GP_WAVE; ++w) {
-        add += wcnt[w][dd];
-        wcnt[w][dd] = 0;
-      }
-      lpos[dd] += add;
-    }
-    __syncthreads();
+    rank[r] = (uint32_t)__popcll(peers & lanemask_lt());
+    if (valid && rank[r] == 0)
+      sm.wo[(r * NW + (int)wave) * RS_MAX_BUCKETS + (int)d] = (uint16_t)__popcll(peers);
   }
+  __syncthreads();
+  // per digit: counts -> offsets within the digit, in record order; the tile's digit
+  // histogram -> local starts and the global placement of each digit's run
+  {
+    uint32_t run = 0;
+    if (tid < nb) {
+      for (int q = 0; q < RS_ITEMS * NW; ++q) {
+        const uint32_t c = sm.wo[q * RS_MAX_BUCKETS + tid];
+        sm.wo[q * RS_MAX_BUCKETS + tid] = (uint16_t)run;
+        run += c;
+      }
+    }
+    uint32_t tot;
+    const uint32_t pre = block_excl_scan(run, &tot);
+    if (tid < nb) {
+      lpos[tid] = pre;
+      delta[tid] = offs[(size_t)tid * nblk + tile] - pre;
+    }
+  }
+  __syncthreads();
+  uint32_t pos[RS_ITEMS];
+#pragma unroll
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    const uint32_t d = (k[r] >> shift) & mask;
+    pos[r] = lpos[d] + sm.wo[(r * NW + (int)wave) * RS_MAX_BUCKETS + (int)d] + rank[r];
+  }
+  __syncthreads();  // the offsets are read; the tile may now overwrite them
+#pragma unroll
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    if (r * RS_THREADS + (int)tid < tn) {
+      sm.t.k[pos[r]] = k[r];
+      sm.t.v[pos[r]] = v[r];
+      if (pout) sm.t.p[pos[r]] = pl[r];
+    }
+  }
+  __syncthreads();
   // write out in local order: global slot = local slot + (global - local start) of the digit
   for (int j = (int)tid; j < tn; j += RS_THREADS) {
-    const uint32_t key = sk[j];
+    const uint32_t key = sm.t.k[j];
     const uint32_t gpos = delta[(key >> shift) & mask] + (uint32_t)j;
     kout[gpos] = key;
-    vout[gpos] = sv[j];
-    if (pout) pout[gpos] = sp[j];
+    vout[gpos] = sm.t.v[j];
+    if (pout) pout[gpos] = sm.t.p[j];
   }
 }
 
@@ -333,7 +344,8 @@ hipError_t launch_radix_sort(uint32_t *keyA, uint32_t *keyB, uint32_t *valA, uin
     if (e != hipSuccess) return e;
     e = launch_exclusive_scan_u32(hist, hist, ((size_t)1 << bits) * nblk, scan_tmp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(RS_THREADS), 0, s, ki,
+    const uint32_t sgrid = (nblk + GP_XCDS - 1) / GP_XCDS * GP_XCDS;
+    hipLaunchKernelGGL(k_rs_scatter, dim3(sgrid), dim3(RS_THREADS), 0, s, ki,
                        ident ? (const uint32_t *)nullptr : vi, ko, vo, n, shift, bits, hist,
                        nblk, px, py, (const double2 *)pi, po);
     e = hipGetLastError();
