@@ -34,7 +34,7 @@ namespace gp {
 #define RS_THREADS 256
 #define RS_ITEMS 8
 #define RS_TILE (RS_THREADS * RS_ITEMS)
-#define RS_MAX_BITS 8
+#define RS_MAX_BITS 9
 #define RS_MAX_BUCKETS (1 << RS_MAX_BITS)
 static_assert(RS_THREADS == SCAN_THREADS, "the tile scan uses the block scan");
 
@@ -190,21 +190,31 @@ size_t radix_hist_elems(size_t n) {
   return (size_t)RS_MAX_BUCKETS * nblk;
 }
 
+// Digit histograms of tpw (1 .. RS_HIST_TILES) consecutive tiles per workgroup, written
+// digit-major (hist[d * nblk + tile]).  With wide digits (many (digit, tile) words) a
+// workgroup takes several tiles, so its counts of one digit are adjacent and the writes
+// come in runs instead of one scattered word per (digit, tile).
+#define RS_HIST_TILES 16
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t *keys, size_t n,
                                                         int shift, int bits, uint32_t *hist,
-                                                        uint32_t nblk) {
-  __shared__ uint32_t cnt[RS_MAX_BUCKETS];
+                                                        uint32_t nblk, uint32_t tpw) {
+  extern __shared__ uint32_t cnt[];  // [tpw][nb]
   const uint32_t nb = 1u << bits, mask = nb - 1u;
-  for (uint32_t d = threadIdx.x; d < nb; d += RS_THREADS) cnt[d] = 0;
+  const uint32_t t0 = blockIdx.x * tpw;
+  const uint32_t nt = nblk - t0 < tpw ? nblk - t0 : tpw;
+  for (uint32_t d = threadIdx.x; d < nt * nb; d += RS_THREADS) cnt[d] = 0;
   __syncthreads();
-  const size_t base = (size_t)blockIdx.x * RS_TILE;
-  for (int r = 0; r < RS_ITEMS; ++r) {
-    size_t i = base + (size_t)r * RS_THREADS + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & mask], 1u);
+  // the workgroup's keys are contiguous; eight loads in flight per thread
+  const size_t base = (size_t)t0 * RS_TILE;
+  const size_t nk = (size_t)nt * RS_TILE < n - base ? (size_t)nt * RS_TILE : n - base;
+#pragma unroll 8
+  for (uint32_t j = threadIdx.x; j < (uint32_t)nk; j += RS_THREADS)
+    atomicAdd(&cnt[(j / RS_TILE) * nb + ((keys[base + j] >> shift) & mask)], 1u);
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < nt * nb; j += RS_THREADS) {
+    const uint32_t d = j / nt, t = j % nt;
+    hist[(size_t)d * nblk + t0 + t] = cnt[t * nb + d];
   }
-  __syncthreads();
-  for (uint32_t d = threadIdx.x; d < nb; d += RS_THREADS)
-    hist[(size_t)d * nblk + blockIdx.x] = cnt[d];
 }
 
 // Payload: pass 0 reads it from the caller's separate x/y arrays (px0, py0), later
@@ -255,8 +265,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     pl[r] = make_double2(0.0, 0.0);
     if (valid && pout) pl[r] = pin ? pin[i] : make_double2(px0[i], py0[i]);
   }
-  for (uint32_t j = tid; j < RS_ITEMS * NW * RS_MAX_BUCKETS / 2; j += RS_THREADS)
-    ((uint32_t *)sm.wo)[j] = 0u;
+  for (uint32_t j = tid; j < RS_ITEMS * NW * nb / 2; j += RS_THREADS) ((uint32_t *)sm.wo)[j] = 0u;
   __syncthreads();
   // rank of every record among the equal digits of its wave and round; the first such
   // lane records their count
@@ -272,25 +281,39 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     }
     rank[r] = (uint32_t)__popcll(peers & lanemask_lt());
     if (valid && rank[r] == 0)
-      sm.wo[(r * NW + (int)wave) * RS_MAX_BUCKETS + (int)d] = (uint16_t)__popcll(peers);
+      sm.wo[(r * NW + (int)wave) * (int)nb + (int)d] = (uint16_t)__popcll(peers);
   }
   __syncthreads();
   // per digit: counts -> offsets within the digit, in record order; the tile's digit
-  // histogram -> local starts and the global placement of each digit's run
+  // histogram -> local starts and the global placement of each digit's run.  Thread t
+  // takes digits dpt*t .. dpt*t + dpt - 1.
   {
-    uint32_t run = 0;
-    if (tid < nb) {
-      for (int q = 0; q < RS_ITEMS * NW; ++q) {
-        const uint32_t c = sm.wo[q * RS_MAX_BUCKETS + tid];
-        sm.wo[q * RS_MAX_BUCKETS + tid] = (uint16_t)run;
-        run += c;
+    constexpr int DPT = RS_MAX_BUCKETS / RS_THREADS > 1 ? RS_MAX_BUCKETS / RS_THREADS : 1;
+    const uint32_t dpt = nb > RS_THREADS ? nb / RS_THREADS : 1u;
+    uint32_t run[DPT], sum = 0;
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+      run[i] = 0;
+      const uint32_t d = tid * dpt + (uint32_t)i;
+      if ((uint32_t)i < dpt && d < nb) {
+        for (int q = 0; q < RS_ITEMS * NW; ++q) {
+          const uint32_t c = sm.wo[q * nb + d];
+          sm.wo[q * nb + d] = (uint16_t)run[i];
+          run[i] += c;
+        }
       }
+      sum += run[i];
     }
     uint32_t tot;
-    const uint32_t pre = block_excl_scan(run, &tot);
-    if (tid < nb) {
-      lpos[tid] = pre;
-      delta[tid] = offs[(size_t)tid * nblk + tile] - pre;
+    uint32_t pre = block_excl_scan(sum, &tot);
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+      const uint32_t d = tid * dpt + (uint32_t)i;
+      if ((uint32_t)i < dpt && d < nb) {
+        lpos[d] = pre;
+        delta[d] = offs[(size_t)d * nblk + tile] - pre;
+        pre += run[i];
+      }
     }
   }
   __syncthreads();
@@ -298,7 +321,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
 #pragma unroll
   for (int r = 0; r < RS_ITEMS; ++r) {
     const uint32_t d = (k[r] >> shift) & mask;
-    pos[r] = lpos[d] + sm.wo[(r * NW + (int)wave) * RS_MAX_BUCKETS + (int)d] + rank[r];
+    pos[r] = lpos[d] + sm.wo[(r * NW + (int)wave) * nb + d] + rank[r];
   }
   __syncthreads();  // the offsets are read; the tile may now overwrite them
 #pragma unroll
@@ -338,8 +361,10 @@ hipError_t launch_radix_sort(uint32_t *keyA, uint32_t *keyB, uint32_t *valA, uin
   bool ident = values_are_identity;
   for (int p = 0; p < passes; ++p) {
     const int shift = p * bits;
-    hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(RS_THREADS), 0, s, ki, n, shift, bits, hist,
-                       nblk);
+    const uint32_t tpw = bits >= 8 ? RS_HIST_TILES : 1;
+    hipLaunchKernelGGL(k_rs_hist, dim3((nblk + tpw - 1) / tpw), dim3(RS_THREADS),
+                       (size_t)tpw * ((size_t)1 << bits) * 4, s, ki, n, shift, bits, hist, nblk,
+                       tpw);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = launch_exclusive_scan_u32(hist, hist, ((size_t)1 << bits) * nblk, scan_tmp, s);
