@@ -71,7 +71,7 @@ struct RefineArgs {
   uint32_t *rq_count;
   int32_t edge_chunk;
   int32_t vp_points;         // items with at most this many points go vertex-parallel
-  uint32_t *vp_list;         // P2P mixed: indices of those items, collected before the
+  uint32_t *vp_list;         // P2P: indices of those items, collected before the
   uint32_t *vp_count;        //   refinement (count zeroed with the counters)
 };
 
