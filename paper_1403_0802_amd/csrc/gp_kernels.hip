@@ -1606,17 +1606,21 @@ __device__ __forceinline__ uint64_t band_cross(float py, const float4 e, uint64_
   return open;
 }
 
-// Mixed PIP refinement of one item from the grid's records: per candidate polygon the
-// records are copied to LDS chunk by chunk and the plain, band and guarded parts of each
-// chunk run their own loops.
+// Mixed PIP refinement of one item from the grid's records.  The cell's candidate
+// polygons are visited in order, each polygon's records in chunks of PIP_PRE_CHUNK slots;
+// the records of the next chunk (of this polygon or the next one still to be tested) are
+// loaded into registers while the current chunk, already in LDS, is tested, so the
+// item waits on one load round trip only at its start.  Each chunk's plain, band and
+// guarded parts run their own loops.
+#define PIP_PRE_CHUNK 128
 template <int PPL>
 __device__ void pipmix_pre_item(const RefineArgs &a, const Item it, float4 *lds) {
   if (it.npts <= a.vp_points) {
     pip_vp_item(a, it);
     return;
   }
+  constexpr int CH = PIP_PRE_CHUNK, PF = CH / GP_WAVE;
   const uint32_t lane = lane_id();
-  const int EC = a.edge_chunk;  // slots per chunk, even
   const double cx = cell_cx(a, (uint32_t)it.cell), cy = cell_cy(a, (uint32_t)it.cell);
   float px[PPL], py[PPL];
   int32_t best[PPL];
@@ -1632,7 +1636,7 @@ __device__ void pipmix_pre_item(const RefineArgs &a, const Item it, float4 *lds)
   // the metadata of the cell's first 64 candidate pairs, one pair per lane, in one round
   // trip, kept in LDS after the chunk: polygon id, first record slot relative to the
   // cell's first, (plain, band) counts
-  int4 *meta = (int4 *)(lds + a.edge_chunk);
+  int4 *meta = (int4 *)(lds + CH);
   const int64_t rbase = a.prec_off[k0], rend = a.prec_off[k1];
   if ((int)lane < k1 - k0) {
     const int32_t k = k0 + (int32_t)lane;
@@ -1640,114 +1644,161 @@ __device__ void pipmix_pre_item(const RefineArgs &a, const Item it, float4 *lds)
     meta[lane] = make_int4(a.cand_id[k], (int32_t)(a.prec_off[k] - rbase), pc.x, pc.y);
   }
   __syncthreads();
-  for (int32_t k = k0; k < k1; ++k) {
+  // candidate pair k: polygon, class, first slot, slots, plain and plain+band counts
+  struct Cand {
+    int32_t f, cls;
+    int64_t r0;
+    int32_t nsl, nP, nPB;
+  };
+  auto cand = [&](int32_t k) {
+    Cand c;
     const int32_t q = k - k0;
-    const bool inreg = q < GP_WAVE;
-    int4 m = make_int4(0, 0, 0, 0);
-    if (inreg) {
-      m = meta[q];
-      m.x = __builtin_amdgcn_readfirstlane(m.x);
-      m.y = __builtin_amdgcn_readfirstlane(m.y);
-      m.z = __builtin_amdgcn_readfirstlane(m.z);
-      m.w = __builtin_amdgcn_readfirstlane(m.w);
+    c.cls = a.cand_class ? a.cand_class[k] : 2;
+    if (q < GP_WAVE) {
+      const int4 m = meta[q];
+      c.f = __builtin_amdgcn_readfirstlane(m.x);
+      c.r0 = rbase + __builtin_amdgcn_readfirstlane(m.y);
+      c.nP = __builtin_amdgcn_readfirstlane(m.z);
+      c.nPB = c.nP + __builtin_amdgcn_readfirstlane(m.w);
+    } else {
+      c.f = a.cand_id[k];
+      c.r0 = a.prec_off[k];
+      const int2 pc = a.pcnt[k];
+      c.nP = pc.x;
+      c.nPB = pc.x + pc.y;
     }
-    const int32_t f = inreg ? m.x : a.cand_id[k];
-    const int cls = a.cand_class ? a.cand_class[k] : 2;
-    if (cls == 0) continue;  // the cell lies outside polygon f
-    if (cls == 1) {          // inside: every undecided point takes f, and all are decided
-#pragma unroll
-      for (int j = 0; j < PPL; ++j)
-        if (best[j] < 0 && !rq[j]) best[j] = f;
-      break;
-    }
-    const int64_t r0 = inreg ? rbase + m.y : a.prec_off[k];
     const int64_t r1 = k + 1 == k1 ? rend
                        : (q + 1 < GP_WAVE ? rbase + __builtin_amdgcn_readfirstlane(meta[q + 1].y)
                                           : a.prec_off[k + 1]);
-    const int32_t nsl = (int32_t)(r1 - r0);
-    const int32_t nP = inreg ? m.z : a.pcnt[k].x;
-    const int32_t nPB = nP + (inreg ? m.w : a.pcnt[k].y);
-    const int32_t gs = (nPB + 1) & ~1;
-    uint64_t par[PPL], flg[PPL];
+    c.nsl = (int32_t)(r1 - c.r0);
+    return c;
+  };
+  // the first candidate at or after k that is not wholly outside the cell (k1 if none)
+  auto next_tested = [&](int32_t k, Cand &c) {
+    for (; k < k1; ++k) {
+      c = cand(k);
+      if (c.cls != 0) break;
+    }
+    return k;
+  };
+  float4 pf[PF];
+  auto prefetch = [&](int64_t r, int cnt) {
 #pragma unroll
-    for (int j = 0; j < PPL; ++j) { par[j] = 0; flg[j] = 0; }
-    for (int32_t s = 0; s < nsl; s += EC) {
-      const int cnt = (nsl - s) < EC ? (nsl - s) : EC;
-      __syncthreads();
-      for (int t = (int)lane; t < cnt; t += GP_WAVE) lds[t] = a.precs[r0 + s + t];
-      __syncthreads();
-      auto clampc = [&](int32_t v) { return v < 0 ? 0 : (v > cnt ? cnt : v); };
-      // plain records [0, p1)
-      const int p1 = clampc(nP - s);
-      int t = 0;
-      for (; t + U <= p1; t += U) {
-        float4 e[U];
+    for (int i = 0; i < PF; ++i) {
+      const int t = (int)lane + GP_WAVE * i;
+      pf[i] = t < cnt ? a.precs[r + t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  Cand cur;
+  int32_t k = next_tested(k0, cur);
+  int32_t s = 0;
+  if (k < k1 && cur.cls == 2) prefetch(cur.r0, cur.nsl < CH ? cur.nsl : CH);
+  uint64_t par[PPL], flg[PPL];
 #pragma unroll
-        for (int q = 0; q < U; ++q) e[q] = lds[t + q];
+  for (int j = 0; j < PPL; ++j) { par[j] = 0; flg[j] = 0; }
+  while (k < k1) {
+    if (cur.cls == 1) {  // inside: every undecided point takes f, and all are decided
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) {
-          uint64_t m = 0;
+      for (int j = 0; j < PPL; ++j)
+        if (best[j] < 0 && !rq[j]) best[j] = cur.f;
+      break;
+    }
+    const int cnt = (cur.nsl - s) < CH ? (cur.nsl - s) : CH;
+    __syncthreads();
 #pragma unroll
-          for (int q = 0; q < U; ++q) m ^= plain_cross(px[j], py[j], e[q]);
-          par[j] ^= m;
-        }
-      }
-      for (; t + 2 <= p1; t += 2) {
-        const float4 e0 = lds[t], e1 = lds[t + 1];
+    for (int i = 0; i < PF; ++i) {
+      const int t = (int)lane + GP_WAVE * i;
+      if (t < cnt) lds[t] = pf[i];
+    }
+    __syncthreads();
+    // the next chunk: the rest of this polygon, else the next polygon to test
+    Cand nxt = cur;
+    int32_t nk = k, ns = s + CH;
+    if (ns >= cur.nsl) {
+      nk = next_tested(k + 1, nxt);
+      ns = 0;
+    }
+    if (nk < k1 && nxt.cls == 2)
+      prefetch(nxt.r0 + ns, (nxt.nsl - ns) < CH ? (nxt.nsl - ns) : CH);
+    const int32_t nP = cur.nP, nPB = cur.nPB, gs = (nPB + 1) & ~1;
+    auto clampc = [&](int32_t v) { return v < 0 ? 0 : (v > cnt ? cnt : v); };
+    // plain records [0, p1)
+    const int p1 = clampc(nP - s);
+    int t = 0;
+    for (; t + U <= p1; t += U) {
+      float4 e[U];
 #pragma unroll
-        for (int j = 0; j < PPL; ++j)
-          par[j] ^= plain_cross(px[j], py[j], e0) ^ plain_cross(px[j], py[j], e1);
-      }
-      if (t < p1) {
-        const float4 e0 = lds[t];
+      for (int q = 0; q < U; ++q) e[q] = lds[t + q];
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) par[j] ^= plain_cross(px[j], py[j], e0);
-      }
-      // band records [p1, b1)
-      const int b1 = clampc(nPB - s);
-      for (t = p1; t + 4 <= b1; t += 4) {
-        const float4 e0 = lds[t], e1 = lds[t + 1], e2 = lds[t + 2], e3 = lds[t + 3];
+      for (int j = 0; j < PPL; ++j) {
+        uint64_t m = 0;
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) {
-          uint64_t amb = 0;
-          par[j] ^= band_cross(py[j], e0, amb) ^ band_cross(py[j], e1, amb) ^
-                    band_cross(py[j], e2, amb) ^ band_cross(py[j], e3, amb);
-          flg[j] |= amb;
-        }
-      }
-      for (; t < b1; ++t) {
-        const float4 e0 = lds[t];
-#pragma unroll
-        for (int j = 0; j < PPL; ++j) {
-          uint64_t amb = 0;
-          par[j] ^= band_cross(py[j], e0, amb);
-          flg[j] |= amb;
-        }
-      }
-      // guarded records, two slots each, from the first even slot after the band ones
-      for (t = clampc(gs - s); t + 2 <= cnt; t += 2) {
-        const float4 e = lds[t];
-        const float G = lds[t + 1].x;
-#pragma unroll
-        for (int j = 0; j < PPL; ++j) {
-          const float ty = py[j] - e.y;
-          const float d = fmaf(ty, e.w, e.x) - px[j];
-          const uint64_t st = ballot(ty >= 0.0f) & ballot(py[j] < e.z);
-          const uint64_t eq = ballot(ty == 0.0f) | ballot(py[j] == e.z);
-          par[j] ^= st & ballot(d > 0.0f);
-          flg[j] |= (eq & ballot(!(d < -G))) | (st & ballot(!(fabsf(d) > G)));
-        }
+        for (int q = 0; q < U; ++q) m ^= plain_cross(px[j], py[j], e[q]);
+        par[j] ^= m;
       }
     }
+    for (; t + 2 <= p1; t += 2) {
+      const float4 e0 = lds[t], e1 = lds[t + 1];
 #pragma unroll
-    for (int j = 0; j < PPL; ++j) {
-      const bool odd = (par[j] >> lane) & 1ull;
-      const bool fl = (flg[j] >> lane) & 1ull;
-      if (best[j] < 0 && !rq[j]) {
-        if (fl) rq[j] = true;
-        else if (odd) best[j] = f;
+      for (int j = 0; j < PPL; ++j)
+        par[j] ^= plain_cross(px[j], py[j], e0) ^ plain_cross(px[j], py[j], e1);
+    }
+    if (t < p1) {
+      const float4 e0 = lds[t];
+#pragma unroll
+      for (int j = 0; j < PPL; ++j) par[j] ^= plain_cross(px[j], py[j], e0);
+    }
+    // band records [p1, b1)
+    const int b1 = clampc(nPB - s);
+    for (t = p1; t + 4 <= b1; t += 4) {
+      const float4 e0 = lds[t], e1 = lds[t + 1], e2 = lds[t + 2], e3 = lds[t + 3];
+#pragma unroll
+      for (int j = 0; j < PPL; ++j) {
+        uint64_t amb = 0;
+        par[j] ^= band_cross(py[j], e0, amb) ^ band_cross(py[j], e1, amb) ^
+                  band_cross(py[j], e2, amb) ^ band_cross(py[j], e3, amb);
+        flg[j] |= amb;
       }
     }
+    for (; t < b1; ++t) {
+      const float4 e0 = lds[t];
+#pragma unroll
+      for (int j = 0; j < PPL; ++j) {
+        uint64_t amb = 0;
+        par[j] ^= band_cross(py[j], e0, amb);
+        flg[j] |= amb;
+      }
+    }
+    // guarded records, two slots each, from the first even slot after the band ones
+    for (t = clampc(gs - s); t + 2 <= cnt; t += 2) {
+      const float4 e = lds[t];
+      const float G = lds[t + 1].x;
+#pragma unroll
+      for (int j = 0; j < PPL; ++j) {
+        const float ty = py[j] - e.y;
+        const float d = fmaf(ty, e.w, e.x) - px[j];
+        const uint64_t st = ballot(ty >= 0.0f) & ballot(py[j] < e.z);
+        const uint64_t eq = ballot(ty == 0.0f) | ballot(py[j] == e.z);
+        par[j] ^= st & ballot(d > 0.0f);
+        flg[j] |= (eq & ballot(!(d < -G))) | (st & ballot(!(fabsf(d) > G)));
+      }
+    }
+    if (nk != k) {  // the polygon is done
+#pragma unroll
+      for (int j = 0; j < PPL; ++j) {
+        const bool odd = (par[j] >> lane) & 1ull;
+        const bool fl = (flg[j] >> lane) & 1ull;
+        if (best[j] < 0 && !rq[j]) {
+          if (fl) rq[j] = true;
+          else if (odd) best[j] = cur.f;
+        }
+        par[j] = 0;
+        flg[j] = 0;
+      }
+    }
+    k = nk;
+    s = ns;
+    cur = nxt;
   }
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
@@ -2652,7 +2703,7 @@ __global__ __launch_bounds__(64 * W) void k_p2pmix_pre(RefineArgs a, int persist
 }
 
 static size_t refine_lds_bytes(gp_kind kind, gp_precision prec, int ec, int W, bool pre) {
-  if (kind == GP_PIP && prec == GP_MIXED && pre) return (size_t)ec * 16 + GP_WAVE * 16;
+  if (kind == GP_PIP && prec == GP_MIXED && pre) return (size_t)PIP_PRE_CHUNK * 16 + GP_WAVE * 16;
   if (kind == GP_PIP)
     return prec == GP_FP64 ? (size_t)ec * sizeof(PipRec64) : (size_t)ec * (16 + 16 + 4);
   if (prec == GP_FP64) return (size_t)ec * (sizeof(SegRec64) + sizeof(int2));
