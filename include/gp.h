@@ -136,7 +136,9 @@ typedef struct gp_grid gp_grid;
 /* Kernel configuration chosen by gp_autotune or set by hand (0 = library default). */
 typedef struct gp_tuning {
     int32_t points_per_lane; /* 1, 2 or 4: a work item holds up to 64*ppl points */
-    int32_t edge_chunk;      /* edges staged in LDS per round: 64..512, multiple of 64 */
+    int32_t edge_chunk;      /* edges staged in LDS per round: 64..512, multiple of 64
+                                (the mixed PIP form on a grid with build-time records
+                                streams fixed chunks of 128 and ignores it) */
     int32_t wg_per_cu;       /* persistent workgroups per compute unit: 1..32 */
     int32_t persistent;      /* 1: persistent workgroups popping items from one queue per
                                 XCD (stealing from the others when theirs is empty);

@@ -1069,7 +1069,12 @@ static gp_status autotune_search(gp_grid *g, gp_precision prec, int64_t n, const
                                  size_t ws_bytes, hipStream_t s, gp_tuning *best,
                                  float *best_ms) {
   std::vector<gp_tuning> space;
-  const int ppls[3] = {1, 2, 4}, ecs[3] = {128, 256, 512}, wgs[4] = {8, 12, 16, 32};
+  const int ppls[3] = {1, 2, 4}, wgs[4] = {8, 12, 16, 32};
+  // the mixed PIP refinement over build-time records streams chunks of a fixed size, so
+  // the LDS chunk is no axis there
+  const bool fixed_chunk = g->kind == GP_PIP && prec == GP_MIXED && g->d_precs != nullptr;
+  const std::vector<int> ecs =
+      fixed_chunk ? std::vector<int>{128} : std::vector<int>{128, 256, 512};
   for (int p : ppls)
     for (int e : ecs)
       for (int wgc : wgs) space.push_back(gp_tuning{p, e, wgc, 1, 1, 0});
