@@ -72,6 +72,14 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
 // Exclusive prefix sum of uint32 in three phases (tile reduce, scan of tile sums,
 // tile scan + offset), recursive over the tile sums.  Deterministic.
 
+// Orders a wave's LDS accesses: every lane's earlier LDS writes are visible to every
+// lane's later reads (one wave executes its LDS instructions in order; the fence keeps
+// the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   const uint32_t lane = lane_id();
 #pragma unroll
@@ -1832,17 +1840,20 @@ __device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
 // Vertex-parallel refinement of a P2P item with few points (the alternative mapping of
 // Sec. III.B, with the cross-lane minimum): lanes take the segments of the cell's
 // candidate polylines, four of the item's points at a time.  Each lane keeps, per point,
-// the smallest distance it has seen within range and the polyline it came from (the
-// candidates ascend by id, so a later equal distance keeps the smaller id); the point's
-// answer is the smallest (distance, id) pair over the lanes, which is the nearest
-// polyline in range with ties to the smaller id.  FP64 in the definition's operation
-// order; a perpendicular quotient is divided out only when it could still beat the
-// lane's best, itself at most next(D*D) (cc >= fl(thr*L2)*(1+2^-49) implies
-// cc/L2 > thr), so the results are the definition's in both precision forms.  No lane
-// waits on another inside the loops: candidate ids and segment ranges arrive 64 at a
-// time in one round trip, and the only cross-lane steps are the final minima.
-__device__ void p2p_vp_item(const RefineArgs &a, const Item it) {
+// the smallest distance it has seen within range and the polyline it came from (a lane
+// meets the segments in ascending polyline order, so a later equal distance keeps the
+// smaller id); the point's answer is the smallest (distance, id) pair over the lanes,
+// which is the nearest polyline in range with ties to the smaller id.  FP64 in the
+// definition's operation order; a perpendicular quotient is divided out only when it
+// could still beat the lane's best, itself at most next(D*D) (cc >= fl(thr*L2)*(1+2^-49)
+// implies cc/L2 > thr), so the results are the definition's in both precision forms.
+// The segments of 64 candidates at a time are laid end to end and the lanes walk that
+// list 64 segments per step (short polylines do not leave lanes idle); each lane finds
+// its segment's polyline from the window's start offsets in LDS (win: this wave's 3 x 64
+// words), and the only cross-lane steps are the window scan and the final minima.
+__device__ void p2p_vp_item(const RefineArgs &a, const Item it, int32_t *win) {
   const uint32_t lane = lane_id();
+  int32_t *wid = win, *wseg = win + GP_WAVE, *wstart = win + 2 * GP_WAVE;
   const int np = it.npts;  // 1 .. a.vp_points (<= 64)
   const int32_t k0 = a.cand_off[it.cell], k1 = a.cand_off[it.cell + 1];
   for (int g = 0; g < np; g += 4) {
@@ -1858,41 +1869,45 @@ __device__ void p2p_vp_item(const RefineArgs &a, const Item it) {
     }
     for (int32_t kw = k0; kw < k1; kw += GP_WAVE) {
       const int32_t kk = kw + (int32_t)lane;
-      int32_t wf = 0, w0 = 0, w1 = 0;
+      const int nk = min(GP_WAVE, k1 - kw);
+      int32_t wf = 0, w0 = 0, len = 0;
       if (kk < k1) {
         wf = a.cand_id[kk];
         w0 = a.eoff[wf];
-        w1 = a.eoff[wf + 1];
+        len = a.eoff[wf + 1] - w0;
       }
-      const int nk = min(GP_WAVE, k1 - kw);
-      for (int q = 0; q < nk; ++q) {
-        const int32_t f = __builtin_amdgcn_readlane(wf, q);
-        const int32_t s1 = __builtin_amdgcn_readlane(w1, q);
-#pragma unroll 1
-        for (int32_t e = __builtin_amdgcn_readlane(w0, q) + (int32_t)lane; e < s1;
-             e += GP_WAVE) {
-          const double4 r = a.edge64[e];
-          const double dx = r.z - r.x, dy = r.w - r.y;
-          const double L2 = dx * dx + dy * dy;
+      const uint32_t incl = wave_incl_scan((uint32_t)len);
+      const int32_t total = (int32_t)__builtin_amdgcn_readlane(incl, GP_WAVE - 1);
+      wave_lds_sync();  // the previous window's reads are done
+      wid[lane] = wf;
+      wseg[lane] = w0;
+      wstart[lane] = (int32_t)incl - len;
+      wave_lds_sync();
+      int c = 0;  // this lane's candidate in the window (its flat indices only grow)
+      for (int32_t F = (int32_t)lane; F < total; F += GP_WAVE) {
+        while (c + 1 < nk && wstart[c + 1] <= F) ++c;
+        const int32_t f = wid[c];
+        const double4 r = a.edge64[wseg[c] + (F - wstart[c])];
+        const double dx = r.z - r.x, dy = r.w - r.y;
+        const double L2 = dx * dx + dy * dy;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const double wx = px[j] - r.x, wy = py[j] - r.y;
-            const double t = wx * dx + wy * dy;
-            double d2;
-            if (t <= 0.0) {
-              d2 = wx * wx + wy * wy;
-            } else if (t >= L2) {
-              const double ex = px[j] - r.z, ey = py[j] - r.w;
-              d2 = ex * ex + ey * ey;
-            } else {
-              const double c = wx * dy - wy * dx;
-              const double cc = c * c;
-              d2 = cc < (best[j] * L2) * (1.0 + 0x1p-49) ? cc / L2 : INFINITY;
-            }
-            if (d2 < best[j]) {
-              best[j] = d2;
-              bid[j] = f;
-            }
+        for (int j = 0; j < 4; ++j) {
+          const double wx = px[j] - r.x, wy = py[j] - r.y;
+          const double t = wx * dx + wy * dy;
+          double d2;
+          if (t <= 0.0) {
+            d2 = wx * wx + wy * wy;
+          } else if (t >= L2) {
+            const double ex = px[j] - r.z, ey = py[j] - r.w;
+            d2 = ex * ex + ey * ey;
+          } else {
+            const double cr = wx * dy - wy * dx;
+            const double cc = cr * cr;
+            d2 = cc < (best[j] * L2) * (1.0 + 0x1p-49) ? cc / L2 : INFINITY;
+          }
+          if (d2 < best[j]) {
+            best[j] = d2;
+            bid[j] = f;
           }
         }
       }
@@ -2066,14 +2081,6 @@ __device__ __forceinline__ uint32_t seg_d2_bits(float px, float py, const float4
 // LDS of the exact-distance pass per wave: for up to two pairs per lane the result,
 // descriptor and threshold, the lanes' points, and a queue of 128 (pair, block) entries.
 #define P2P_EPI_BYTES (2 * GP_WAVE * (8 + 16 + 8 + 8) + GP_WAVE * 16)
-
-// Orders a wave's LDS accesses: every lane's earlier LDS writes are visible to every
-// lane's later reads (one wave executes its LDS instructions in order; the fence keeps
-// the compiler from moving them).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
 
 // One segment's record for a cell with centre c: its frame constants relative to c
 // (s_c = -(m - c).u, r_c = -(m - c).v, scaled), its error bound e_s in distance units,
@@ -2684,11 +2691,12 @@ __global__ __launch_bounds__(256) void k_vp_collect(RefineArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_p2p_vp(RefineArgs a) {
+  __shared__ int32_t win[256 / GP_WAVE][3 * GP_WAVE];
   const uint32_t nvp = *a.vp_count;
   const uint32_t waves = gridDim.x * (blockDim.x / GP_WAVE);
   for (uint32_t q = blockIdx.x * (blockDim.x / GP_WAVE) + threadIdx.x / GP_WAVE; q < nvp;
        q += waves)
-    p2p_vp_item(a, a.items[a.vp_list[q]]);
+    p2p_vp_item(a, a.items[a.vp_list[q]], win[threadIdx.x / GP_WAVE]);
 }
 
 template <int PPL, int W>
