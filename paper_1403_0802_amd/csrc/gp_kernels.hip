@@ -1159,8 +1159,10 @@ __device__ __forceinline__ void load_points32(const RefineArgs &a, const Item it
   for (int j = 0; j < PPL; ++j) {
     const int idx = (int)lane + GP_WAVE * j;
     const double2 p = idx < it.npts ? a.xy[it.pt_lo + idx] : make_double2(cx, cy);
-    px[j] = (float)(p.x - cx);
-    py[j] = (float)(p.y - cy);
+    // + 0 turns a rebased -0 into +0, so the tests on bit patterns (u32 compares of
+    // p.y - lo.y) see a point level with an endpoint as t = +0
+    px[j] = (float)(p.x - cx) + 0.0f;
+    py[j] = (float)(p.y - cy) + 0.0f;
   }
 }
 
@@ -1605,13 +1607,14 @@ hipError_t launch_pip_rec_emit(const uint32_t *pair_cell, const int32_t *cand_id
 }
 
 // Band test of one edge record: the open straddle 0 < t < h of each lane's point (the
-// crossing), and into amb the lanes with t = 0 or t = h (closed but not open).
-__device__ __forceinline__ uint64_t band_cross(float py, const float4 e, uint64_t &amb) {
+// crossing, as a lane mask).  A point level with an endpoint (t = 0 or t = h, closed but
+// not open) is ambiguous: amb, per lane, keeps the minimum of t and t ^ h as bit
+// patterns, which is zero once that has happened.  Kept in a VGPR, the ambiguity costs
+// vector instructions only; the scalar unit, which bounds this kernel, sees one XOR.
+__device__ __forceinline__ uint64_t band_cross(float py, const float4 e, uint32_t &amb) {
   const uint32_t tb = __float_as_uint(py - e.x);
-  const uint64_t open = ballot(tb - 1u < __float_as_uint(e.y));
-  const uint64_t closed = ballot(tb <= __float_as_uint(e.z));
-  amb |= closed & ~open;
-  return open;
+  amb = min(amb, min(tb, tb ^ __float_as_uint(e.z)));
+  return ballot(tb - 1u < __float_as_uint(e.y));
 }
 
 // Mixed PIP refinement of one item from the grid's records.  The cell's candidate
@@ -1702,8 +1705,9 @@ __device__ void pipmix_pre_item(const RefineArgs &a, const Item it, float4 *lds)
   int32_t s = 0;
   if (k < k1 && cur.cls == 2) prefetch(cur.r0, cur.nsl < CH ? cur.nsl : CH);
   uint64_t par[PPL], flg[PPL];
+  uint32_t ambv[PPL];  // per lane: zero once the point is level with a band endpoint
 #pragma unroll
-  for (int j = 0; j < PPL; ++j) { par[j] = 0; flg[j] = 0; }
+  for (int j = 0; j < PPL; ++j) { par[j] = 0; flg[j] = 0; ambv[j] = ~0u; }
   while (k < k1) {
     if (cur.cls == 1) {  // inside: every undecided point takes f, and all are decided
 #pragma unroll
@@ -1761,21 +1765,14 @@ __device__ void pipmix_pre_item(const RefineArgs &a, const Item it, float4 *lds)
     for (t = p1; t + 4 <= b1; t += 4) {
       const float4 e0 = lds[t], e1 = lds[t + 1], e2 = lds[t + 2], e3 = lds[t + 3];
 #pragma unroll
-      for (int j = 0; j < PPL; ++j) {
-        uint64_t amb = 0;
-        par[j] ^= band_cross(py[j], e0, amb) ^ band_cross(py[j], e1, amb) ^
-                  band_cross(py[j], e2, amb) ^ band_cross(py[j], e3, amb);
-        flg[j] |= amb;
-      }
+      for (int j = 0; j < PPL; ++j)
+        par[j] ^= band_cross(py[j], e0, ambv[j]) ^ band_cross(py[j], e1, ambv[j]) ^
+                  band_cross(py[j], e2, ambv[j]) ^ band_cross(py[j], e3, ambv[j]);
     }
     for (; t < b1; ++t) {
       const float4 e0 = lds[t];
 #pragma unroll
-      for (int j = 0; j < PPL; ++j) {
-        uint64_t amb = 0;
-        par[j] ^= band_cross(py[j], e0, amb);
-        flg[j] |= amb;
-      }
+      for (int j = 0; j < PPL; ++j) par[j] ^= band_cross(py[j], e0, ambv[j]);
     }
     // guarded records, two slots each, from the first even slot after the band ones
     for (t = clampc(gs - s); t + 2 <= cnt; t += 2) {
@@ -1795,13 +1792,14 @@ __device__ void pipmix_pre_item(const RefineArgs &a, const Item it, float4 *lds)
 #pragma unroll
       for (int j = 0; j < PPL; ++j) {
         const bool odd = (par[j] >> lane) & 1ull;
-        const bool fl = (flg[j] >> lane) & 1ull;
+        const bool fl = ((flg[j] >> lane) & 1ull) || ambv[j] == 0u;
         if (best[j] < 0 && !rq[j]) {
           if (fl) rq[j] = true;
           else if (odd) best[j] = cur.f;
         }
         par[j] = 0;
         flg[j] = 0;
+        ambv[j] = ~0u;
       }
     }
     k = nk;
