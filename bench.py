@@ -107,7 +107,7 @@ WORKLOAD_NAME = "C3 PIP 50M pts x 5000 polygons + C4 P2P 200M pts x 200000 polyl
 # The grids of the step (the full-size parity tests build the same ones).  PIP: 1/512, the
 # fastest PIP query of the cell-size sweep (bench.py --cell-sweep), with build-time
 # per-(cell, polygon) edge records (prestage).  P2P: 100 m cells with
-# build-time segment records (p2p_prestage), an index structure like the candidate lists;
+# build-time segment records (prestage), an index structure like the candidate lists;
 # detail.p2p_plain_grid runs the grid without them.
 PIP_GRID = dict(cell_size=1 / 512, nx=512, ny=512, prestage=1)
 P2P_GRID = dict(cell_size=100.0, radius_D=100.0, nx=400, ny=400, prestage=1)

@@ -100,7 +100,7 @@ struct Grid {
   int64_t *d_cell_segs;   // [ncells] segments per cell
   int64_t ncseg;
   int2 *d_near;           // P2P: near-segment range per (cell, candidate) pair
-  float4 *d_recU;         // P2P build-time staging (p2p_prestage)
+  float4 *d_recU;         // P2P build-time staging (prestage)
   float *d_recV;
   int64_t *d_rec_off;
   float2 *d_cellE;
