@@ -202,3 +202,49 @@ def test_signed_zero_coordinates(gp):
             for tuning in (None, dict(vp_points=-1), dict(vp_points=64)):
                 got = gpu_run(gp, grid, px, py, prec, tuning)
                 assert np.array_equal(got, want), (pre, prec, tuning, int(np.sum(got != want)))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_pip_item_sizes(gp, seed):
+    """Every count of points per cell from 1 to 300 (so every split of a cell into items:
+    full items and remainders of every size, each run with the fewest points per lane that
+    hold it), on overlapping star polygons with holes, with points level with and on
+    vertices inside each cell: the prestaged mixed form equals the oracle, with and
+    without the vertex-parallel path for few-point items, at 1, 2 and 4 points per lane."""
+    rng = np.random.default_rng(7100 + seed)
+    xs, ys, roff, froff = [], [], [0], [0]
+    for _ in range(12):
+        cx, cy = rng.uniform(2, 18, 2)
+        r = rng.uniform(2, 6)
+        m = int(rng.integers(20, 300))
+        x, y, _, _ = synth.star_ring(rng, cx, cy, m, 0.5 * r, r)
+        xs.append(x), ys.append(y), roff.append(roff[-1] + m)
+        if rng.random() < 0.5:
+            mh = int(rng.integers(3, 40))
+            x, y, _, _ = synth.star_ring(rng, cx, cy, mh, 0.05 * r, 0.4 * r)
+            xs.append(x[::-1]), ys.append(y[::-1]), roff.append(roff[-1] + mh)
+        froff.append(len(roff) - 1)
+    vx, vy = np.concatenate(xs), np.concatenate(ys)
+    geom = synth.Geometry("pip", np.asarray(roff, np.int64), vx, vy, np.asarray(froff, np.int64))
+    params = synth.GridParams(cell_size=1.0, x0=0.0, y0=0.0, nx=20, ny=20)
+    counts = rng.permutation(np.arange(1, 401)) % 300 + 1  # 400 cells, every count 1..300
+    pxs, pys = [], []
+    for c, k in enumerate(counts):
+        i, j = c % 20, c // 20
+        px = i + rng.uniform(0, 1, k)
+        py = j + rng.uniform(0, 1, k)
+        inside = np.nonzero((vx >= i) & (vx < i + 1) & (vy >= j) & (vy < j + 1))[0]
+        if len(inside) and k >= 4:
+            q = rng.choice(inside, k // 4)
+            py[: k // 4] = vy[q]  # level with a vertex of the cell
+            px[k // 8: k // 4] = vx[q[k // 8:]]  # on the vertex itself
+        pxs.append(px), pys.append(py)
+    px, py = np.concatenate(pxs), np.concatenate(pys)
+    og = oracle.build_grid(geom, params)
+    want = oracle.pip(geom, px, py, og)
+    say(f"item sizes seed {seed}: {len(px)} points, {int(np.sum(want >= 0))} inside")
+    grid = gp.gp_build_grid("pip", geom, synth.GridParams(**{**params.__dict__, "prestage": 1}))
+    for tuning in (dict(vp_points=-1), None, dict(points_per_lane=1, vp_points=-1),
+                   dict(points_per_lane=4, vp_points=-1)):
+        got = gpu_run(gp, grid, px, py, "mixed", tuning)
+        assert np.array_equal(got, want), (seed, tuning, int(np.sum(got != want)))
