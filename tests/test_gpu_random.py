@@ -248,3 +248,53 @@ def test_pip_item_sizes(gp, seed):
                    dict(points_per_lane=4, vp_points=-1)):
         got = gpu_run(gp, grid, px, py, "mixed", tuning)
         assert np.array_equal(got, want), (seed, tuning, int(np.sum(got != want)))
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_p2p_item_sizes(gp, seed):
+    """P2P with every count of points per cell from 1 to 600 (full 256-point items and
+    remainders of every size), points near the polylines, on the vertices and at about D
+    from them: ids and distances equal the oracle's in both precision forms, with and
+    without build-time records and the vertex-parallel path, at 1, 2 and 4 points per
+    lane and with two waves per item."""
+    rng = np.random.default_rng(7300 + seed)
+    nl = 150
+    g = synth.random_walk_polylines(rng, nl, rng.integers(2, 30, nl), 0.0, 24.0, 0.05, 0.6)
+    geom = synth.Geometry("p2p", g.ring_vert_off, g.x, g.y, None)
+    D = 0.7
+    # unit cells over the polylines' boxes grown by D, and one more cell on each side
+    x0, y0 = np.floor(g.x.min() - D) - 1.0, np.floor(g.y.min() - D) - 1.0
+    nx, ny = int(np.ceil(g.x.max() + D) - x0) + 1, int(np.ceil(g.y.max() + D) - y0) + 1
+    assert nx * ny >= 600
+    params = synth.GridParams(cell_size=1.0, radius_D=D, x0=x0, y0=y0, nx=nx, ny=ny)
+    counts = rng.permutation(np.arange(1, nx * ny + 1)) % 600 + 1  # every count 1..600
+    pxs, pys = [], []
+    for c, k in enumerate(counts):
+        i, j = c % nx, c // nx
+        px = x0 + i + rng.uniform(0, 1, k)
+        py = y0 + j + rng.uniform(0, 1, k)
+        near = np.nonzero((g.x >= px.min()) & (g.x < px.max()) &
+                          (g.y >= py.min()) & (g.y < py.max()))[0]
+        if len(near) and k >= 4:
+            q = rng.choice(near, k // 2)
+            ang = rng.uniform(0, 2 * np.pi, k // 2)
+            rad = np.where(np.arange(k // 2) % 4 == 0, 0.0, D * rng.uniform(0.98, 1.02, k // 2))
+            px[: k // 2] = g.x[q] + rad * np.cos(ang)
+            py[: k // 2] = g.y[q] + rad * np.sin(ang)
+        pxs.append(px), pys.append(py)
+    px, py = np.concatenate(pxs), np.concatenate(pys)
+    og = oracle.build_grid(geom, params)
+    want_id, want_d = oracle.p2p(geom, px, py, D, og)
+    say(f"p2p item sizes seed {seed}: {len(px)} points, {int(np.sum(want_id >= 0))} in range")
+    for pre in (0, 1):
+        grid = gp.gp_build_grid("p2p", geom, synth.GridParams(**{**params.__dict__,
+                                                                 "prestage": pre}))
+        for prec, tunings in (("mixed", (None, dict(vp_points=-1), dict(points_per_lane=1),
+                                         dict(points_per_lane=2, vp_points=-1),
+                                         dict(points_per_lane=4, waves_per_item=2))),
+                              ("fp64", (None, dict(points_per_lane=4, vp_points=-1)))):
+            for tuning in tunings:
+                got_id, got_d = gpu_run(gp, grid, px, py, prec, tuning)
+                assert np.array_equal(got_id, want_id), (seed, pre, prec, tuning,
+                                                         int(np.sum(got_id != want_id)))
+                assert np.array_equal(got_d, want_d), (seed, pre, prec, tuning)
