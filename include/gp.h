@@ -142,7 +142,10 @@ typedef struct gp_tuning {
     int32_t wg_per_cu;       /* persistent workgroups per compute unit: 1..32 */
     int32_t persistent;      /* 1: persistent workgroups popping items from one queue per
                                 XCD (stealing from the others when theirs is empty);
-                                0: one workgroup per item */
+                                0: one workgroup per item.  While a grid runs the library
+                                default (no gp_set_tuning or gp_autotune on it), queries
+                                of fewer than 2^22 points run one workgroup per item, as
+                                do the server's chunks of fewer than 2^22 points */
     int32_t waves_per_item;  /* P2P: 1, 2 or 4 wavefronts share one LDS staging and a work
                                 item holds up to 64*ppl*waves points; PIP: always 1 */
     int32_t vp_points;       /* items with at most this many points (1..64) use the

@@ -255,6 +255,7 @@ extern "C" gp_status gp_build_grid(gp_kind kind, const gp_geometry *geom,
   g->nedges = (int32_t)nedges;
   g->tune[GP_FP64] = default_tuning(kind, GP_FP64);
   g->tune[GP_MIXED] = default_tuning(kind, GP_MIXED);
+  g->tune_explicit[GP_FP64] = g->tune_explicit[GP_MIXED] = false;
 
 #define GP_TRY_HIP_G(expr)                                                                \
   do {                                                                                    \
@@ -706,7 +707,11 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   const size_t need = workspace_layout(*g, n, prec, ws, &w);
   if (!ws || ws_bytes < need)
     return set_error(GP_E_INVALID_ARG, "workspace too small: %zu bytes needed", need);
-  const gp_tuning t = override_tuning ? *override_tuning : g->tune[prec];
+  gp_tuning t = override_tuning ? *override_tuning : g->tune[prec];
+  // The library default's persistent queue has a cost at the end of every launch (each
+  // workgroup finds the queues empty) that only a large query amortises: below
+  // kPersistentMinPoints the default runs one workgroup per item instead.
+  if (!override_tuning && !g->tune_explicit[prec] && n < kPersistentMinPoints) t.persistent = 0;
   if (!tuning_valid(t, g->kind)) return set_error(GP_E_INVALID_ARG, "invalid tuning");
 
   hipEvent_t ev[5] = {};
@@ -869,6 +874,7 @@ extern "C" gp_status gp_set_tuning(gp_grid *g, gp_precision prec, const gp_tunin
   if (prec != GP_FP64 && prec != GP_MIXED) return set_error(GP_E_INVALID_ARG, "bad precision");
   if (!t) {  // back to the library default
     g->tune[prec] = default_tuning(g->kind, prec);
+    g->tune_explicit[prec] = false;
     return GP_OK;
   }
   gp_tuning v = *t;
@@ -880,6 +886,7 @@ extern "C" gp_status gp_set_tuning(gp_grid *g, gp_precision prec, const gp_tunin
   if (v.vp_points == 0) v.vp_points = d.vp_points;
   if (!tuning_valid(v, g->kind)) return set_error(GP_E_INVALID_ARG, "invalid tuning");
   g->tune[prec] = v;
+  g->tune_explicit[prec] = true;
   return GP_OK;
 }
 
@@ -1051,6 +1058,7 @@ extern "C" gp_status gp_autotune(gp_grid *g, gp_precision prec, int64_t n, const
                        ws_bytes, s, hit, &ms, nullptr);
       if (rc) return rc;
       g->tune[prec] = hit;
+      g->tune_explicit[prec] = true;
       if (best) *best = hit;
       if (best_ms) *best_ms = ms;
       return GP_OK;
@@ -1114,6 +1122,7 @@ static gp_status autotune_search(gp_grid *g, gp_precision prec, int64_t n, const
     }
   }
   g->tune[prec] = best_cfg;
+  g->tune_explicit[prec] = true;
   if (best) *best = best_cfg;
   if (best_ms) *best_ms = best_t;
   return GP_OK;

@@ -272,6 +272,7 @@ static gp_status enqueue_chunk(gp_server *srv, Lane &ln, Request *r, Block *blk,
   tn.waves_per_item = 1;
   const int ppl_cap = b >= (1 << 20) ? 4 : b >= (1 << 17) ? 2 : 1;
   if (tn.points_per_lane > ppl_cap) tn.points_per_lane = ppl_cap;
+  if (b < kPersistentMinPoints) tn.persistent = 0;
   // with under 4 points per cell on average most items hold a few points: those run
   // vertex-parallel (lanes over edges or segments) instead of leaving most lanes idle
   if (tn.vp_points < 0 && (double)b < 4.0 * (double)((const Grid *)g)->ncells)
