@@ -220,6 +220,42 @@ def cpu_simd_run(c3, c4, budget_s: float):
     return out
 
 
+def autotune_small_run(gp, torch):
+    """The autotuner on the two small configurations (PIP C1, 50K points; P2P C2, 1M
+    points), whose points per cell are far from the full-size workloads the library
+    defaults come from: the query time with the default and with the tuned configuration
+    (median of 7 after one untimed query), and the winner."""
+    from paper_1403_0802_amd import synth
+    dev = torch.device("cuda")
+    rows = {}
+    for w in (synth.config1(), synth.config2()):
+        grid = gp.gp_build_grid(w.kind, w.geom, w.params)
+        x = torch.from_numpy(np.ascontiguousarray(w.px)).to(dev)
+        y = torch.from_numpy(np.ascontiguousarray(w.py)).to(dev)
+        oid = torch.empty(x.numel(), dtype=torch.int32, device=dev)
+        od = torch.empty(x.numel(), dtype=torch.float64, device=dev)
+        ws = gp.new_workspace(grid, x.numel(), "mixed")
+
+        def query(st):
+            if w.kind == "pip":
+                return gp.gp_pip(grid, x, y, oid, "mixed", ws, None, st)
+            return gp.gp_p2p(grid, x, y, oid, od, "mixed", ws, None, st)
+
+        def timed():
+            query(False)
+            return float(np.median([query(True)["ms_total"] for _ in range(7)]))
+
+        gp.gp_reset_tuning(grid, "mixed")
+        t_default = timed()
+        tuning, _ = gp.gp_autotune(grid, "mixed", x, y, ws)
+        t_tuned = timed()
+        rows[w.name] = {"points": x.numel(), "default_ms": t_default, "tuned_ms": t_tuned,
+                        "tuning": tuning}
+        log(f"[bench] autotune {w.name}: default {t_default:.3f} ms, tuned {t_tuned:.3f} ms")
+        del grid, ws
+    return rows
+
+
 def serving_run(gp, torch, grid3, grid4, pools, n_requests: int, n_warmup: int, precision: str,
                 n_slots=4, slot_points=1 << 22, mem_budget=24 << 30):
     """Configuration 5: a Poisson stream of mixed PIP/P2P requests (log-uniform 1K-4M
@@ -628,6 +664,8 @@ def main():
             "sustained_pts_per_s", "points_per_s", "sample_equal_to_direct_calls")}
         log(f"[bench] serving on the headline grids: p50 {h_['p50_us']:.0f} us, "
             f"p99 {h_['p99_us']:.0f} us")
+    if not args.no_autotune:
+        detail["autotune_small"] = autotune_small_run(gp, torch)
     out = {
         "metric": METRIC,
         "value": value,
