@@ -144,8 +144,10 @@ typedef struct gp_tuning {
                                 XCD (stealing from the others when theirs is empty);
                                 0: one workgroup per item.  While a grid runs the library
                                 default (no gp_set_tuning or gp_autotune on it), queries
-                                of fewer than 2^22 points run one workgroup per item, as
-                                do the server's chunks of fewer than 2^22 points */
+                                of fewer than 2^22 points run one workgroup per item, and
+                                queries of fewer than 256 points per grid cell at most 2
+                                points per lane; the server applies both rules to its
+                                chunks whatever the grid's tuning */
     int32_t waves_per_item;  /* P2P: 1, 2 or 4 wavefronts share one LDS staging and a work
                                 item holds up to 64*ppl*waves points; PIP: always 1 */
     int32_t vp_points;       /* items with at most this many points (1..64) use the

@@ -711,7 +711,11 @@ static gp_status run_query(const gp_grid *g, gp_kind kind, int64_t n, const doub
   // The library default's persistent queue has a cost at the end of every launch (each
   // workgroup finds the queues empty) that only a large query amortises: below
   // kPersistentMinPoints the default runs one workgroup per item instead.
-  if (!override_tuning && !g->tune_explicit[prec] && n < kPersistentMinPoints) t.persistent = 0;
+  if (!override_tuning && !g->tune_explicit[prec]) {
+    if (n < kPersistentMinPoints) t.persistent = 0;
+    if (t.points_per_lane > 2 && n < kFourPerLaneMinPointsPerCell * g->ncells)
+      t.points_per_lane = 2;
+  }
   if (!tuning_valid(t, g->kind)) return set_error(GP_E_INVALID_ARG, "invalid tuning");
 
   hipEvent_t ev[5] = {};

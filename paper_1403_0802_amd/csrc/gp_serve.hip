@@ -270,7 +270,8 @@ static gp_status enqueue_chunk(gp_server *srv, Lane &ln, Request *r, Block *blk,
   // per cell: keep work items to one wavefront and fewer points per lane there.
   gp_tuning tn = ((const Grid *)g)->tune[prec];
   tn.waves_per_item = 1;
-  const int ppl_cap = b >= (1 << 20) ? 4 : b >= (1 << 17) ? 2 : 1;
+  int ppl_cap = b >= (1 << 20) ? 4 : b >= (1 << 17) ? 2 : 1;
+  if (ppl_cap > 2 && b < kFourPerLaneMinPointsPerCell * ((const Grid *)g)->ncells) ppl_cap = 2;
   if (tn.points_per_lane > ppl_cap) tn.points_per_lane = ppl_cap;
   if (b < kPersistentMinPoints) tn.persistent = 0;
   // with under 4 points per cell on average most items hold a few points: those run
