@@ -199,9 +199,10 @@ size_t radix_hist_elems(size_t n) {
 }
 
 // Digit histograms of tpw (1 .. RS_HIST_TILES) consecutive tiles per workgroup, written
-// digit-major (hist[d * nblk + tile]).  With wide digits (many (digit, tile) words) a
-// workgroup takes several tiles, so its counts of one digit are adjacent and the writes
-// come in runs instead of one scattered word per (digit, tile).
+// digit-major (hist[d * nblk + tile]).  A workgroup takes several tiles, so its counts of
+// one digit are adjacent and the writes come in runs instead of one scattered word per
+// (digit, tile).  Each thread loads its RS_ITEMS keys of a tile before counting them, so
+// that they are in flight together (a load-then-count loop waits on every load).
 #define RS_HIST_TILES 16
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t *keys, size_t n,
                                                         int shift, int bits, uint32_t *hist,
@@ -212,12 +213,23 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t *keys, si
   const uint32_t nt = nblk - t0 < tpw ? nblk - t0 : tpw;
   for (uint32_t d = threadIdx.x; d < nt * nb; d += RS_THREADS) cnt[d] = 0;
   __syncthreads();
-  // the workgroup's keys are contiguous; eight loads in flight per thread
+  // the workgroup's keys are contiguous
   const size_t base = (size_t)t0 * RS_TILE;
-  const size_t nk = (size_t)nt * RS_TILE < n - base ? (size_t)nt * RS_TILE : n - base;
-#pragma unroll 8
-  for (uint32_t j = threadIdx.x; j < (uint32_t)nk; j += RS_THREADS)
-    atomicAdd(&cnt[(j / RS_TILE) * nb + ((keys[base + j] >> shift) & mask)], 1u);
+  const uint32_t nk =
+      (uint32_t)((size_t)nt * RS_TILE < n - base ? (size_t)nt * RS_TILE : n - base);
+  for (uint32_t t = 0; t < nt; ++t) {
+    uint32_t kv[RS_ITEMS];
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+      const uint32_t j = t * RS_TILE + r * RS_THREADS + threadIdx.x;
+      kv[r] = j < nk ? keys[base + j] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+      const uint32_t j = t * RS_TILE + r * RS_THREADS + threadIdx.x;
+      if (j < nk) atomicAdd(&cnt[t * nb + ((kv[r] >> shift) & mask)], 1u);
+    }
+  }
   __syncthreads();
   for (uint32_t j = threadIdx.x; j < nt * nb; j += RS_THREADS) {
     const uint32_t d = j / nt, t = j % nt;
@@ -369,7 +381,7 @@ hipError_t launch_radix_sort(uint32_t *keyA, uint32_t *keyB, uint32_t *valA, uin
   bool ident = values_are_identity;
   for (int p = 0; p < passes; ++p) {
     const int shift = p * bits;
-    const uint32_t tpw = bits >= 8 ? RS_HIST_TILES : 1;
+    const uint32_t tpw = RS_HIST_TILES;
     hipLaunchKernelGGL(k_rs_hist, dim3((nblk + tpw - 1) / tpw), dim3(RS_THREADS),
                        (size_t)tpw * ((size_t)1 << bits) * 4, s, ki, n, shift, bits, hist, nblk,
                        tpw);
