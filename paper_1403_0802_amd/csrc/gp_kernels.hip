@@ -1118,22 +1118,29 @@ __device__ __forceinline__ double seg_d2_64(double px, double py, double ax, dou
 // round-robin by index), so the items of one cell share an L2 and its staged edges or
 // segment records are fetched from HBM once.  A workgroup whose queue is exhausted takes
 // items from the next queues: every item is handed out exactly once, and each pop ends
-// after at most GP_XCDS exhausted queues.  Returns n_items when nothing is left.
-__device__ __forceinline__ uint32_t pop_item(const RefineArgs &a, uint32_t n_items) {
+// after at most GP_XCDS exhausted queues.  Returns n_items when nothing is left.  dead
+// (one bit per queue, kept by the caller across its pops) marks the queues this
+// workgroup has found exhausted, so that it asks each of them once: at the end of a
+// launch the failed atomics of all workgroups queue up on the few counter addresses.
+__device__ __forceinline__ uint32_t pop_item(const RefineArgs &a, uint32_t n_items,
+                                             uint32_t &dead) {
   const uint32_t home = blockIdx.x % GP_XCDS;
   for (uint32_t k = 0; k < GP_XCDS; ++k) {
     const uint32_t q = (home + k) % GP_XCDS;
+    if ((dead >> q) & 1u) continue;
     const uint32_t c = atomicAdd(a.item_counter + q, 1u);
     // the c-th item of queue q; increasing in c, so the first miss exhausts the queue
     const uint64_t it = ((uint64_t)(c / GP_XBLOCK) * GP_XCDS + q) * GP_XBLOCK + c % GP_XBLOCK;
     if (it < n_items) return (uint32_t)it;
+    dead |= 1u << q;
   }
   return n_items;
 }
 
-__device__ __forceinline__ uint32_t next_item(const RefineArgs &a, uint32_t n_items) {
+__device__ __forceinline__ uint32_t next_item(const RefineArgs &a, uint32_t n_items,
+                                              uint32_t &dead) {
   uint32_t it = 0;
-  if (lane_id() == 0) it = pop_item(a, n_items);
+  if (lane_id() == 0) it = pop_item(a, n_items, dead);
   return uniform(it);
 }
 
@@ -2557,11 +2564,12 @@ __global__ __launch_bounds__(64) void k_pip64(RefineArgs a, int persistent) {
   extern __shared__ __align__(16) unsigned char smem[];
   PipRec64 *lds = (PipRec64 *)smem;
   const uint32_t n_items = *a.n_items;
-  uint32_t it = persistent ? next_item(a, n_items) : blockIdx.x;
+  uint32_t dead = 0;  // queues this workgroup has found exhausted
+  uint32_t it = persistent ? next_item(a, n_items, dead) : blockIdx.x;
   while (it < n_items) {
     pip64_item<PPL>(a, a.items[it], lds);
     if (!persistent) break;
-    it = next_item(a, n_items);
+    it = next_item(a, n_items, dead);
   }
 }
 
@@ -2572,7 +2580,8 @@ __global__ __launch_bounds__(64) void k_pipmix(RefineArgs a, int persistent) {
   float4 *B = A + a.edge_chunk;
   float *G = (float *)(B + a.edge_chunk);
   const uint32_t n_items = *a.n_items;
-  uint32_t it = persistent ? next_item(a, n_items) : blockIdx.x;
+  uint32_t dead = 0;  // queues this workgroup has found exhausted
+  uint32_t it = persistent ? next_item(a, n_items, dead) : blockIdx.x;
   while (it < n_items) {
     // A cell's last item holds the remainder of its points: it runs with the fewest
     // points per lane that hold them, so its idle point slots cost no tests.
@@ -2581,7 +2590,7 @@ __global__ __launch_bounds__(64) void k_pipmix(RefineArgs a, int persistent) {
     else if (PPL >= 2 && item.npts <= 64) pipmix_item<1>(a, item, A, B, G);
     else pipmix_item<PPL>(a, item, A, B, G);
     if (!persistent) break;
-    it = next_item(a, n_items);
+    it = next_item(a, n_items, dead);
   }
 }
 
@@ -2608,7 +2617,8 @@ __global__ __launch_bounds__(64) void k_pipmix_pre(RefineArgs a, int persistent)
   extern __shared__ __align__(16) unsigned char smem[];
   float4 *lds = (float4 *)smem;
   const uint32_t n_items = *a.n_items;
-  uint32_t it = persistent ? next_item(a, n_items) : xcd_item(blockIdx.x);
+  uint32_t dead = 0;  // queues this workgroup has found exhausted
+  uint32_t it = persistent ? next_item(a, n_items, dead) : xcd_item(blockIdx.x);
   while (it < n_items) {
     // a cell's last item runs with the fewest points per lane that hold its points
     const Item item = a.items[it];
@@ -2618,15 +2628,15 @@ __global__ __launch_bounds__(64) void k_pipmix_pre(RefineArgs a, int persistent)
     else pipmix_pre_item<PPL>(a, item, lds);
     __builtin_amdgcn_s_setprio(0);
     if (!persistent) break;
-    it = next_item(a, n_items);
+    it = next_item(a, n_items, dead);
   }
 }
 
 // Work-queue pop for a workgroup of several waves (broadcast through LDS).
 __device__ __forceinline__ uint32_t next_item_wg(const RefineArgs &a, uint32_t n_items,
-                                                 uint32_t *slot) {
+                                                 uint32_t *slot, uint32_t &dead) {
   __syncthreads();
-  if (threadIdx.x == 0) *slot = pop_item(a, n_items);
+  if (threadIdx.x == 0) *slot = pop_item(a, n_items, dead);
   __syncthreads();
   return *slot;
 }
@@ -2638,13 +2648,14 @@ __global__ __launch_bounds__(64 * W) void k_p2p64(RefineArgs a, int persistent) 
   SegRec64 *lds = (SegRec64 *)smem;
   int2 *tab = (int2 *)(lds + a.edge_chunk);
   const uint32_t n_items = *a.n_items;
-  uint32_t it = persistent ? (W == 1 ? next_item(a, n_items)
-                                      : next_item_wg(a, n_items, &s_item))
+  uint32_t dead = 0;  // queues this workgroup has found exhausted
+  uint32_t it = persistent ? (W == 1 ? next_item(a, n_items, dead)
+                                      : next_item_wg(a, n_items, &s_item, dead))
                            : blockIdx.x;
   while (it < n_items) {
     p2p64_item<PPL, W>(a, a.items[it], lds, tab);
     if (!persistent) break;
-    it = W == 1 ? next_item(a, n_items) : next_item_wg(a, n_items, &s_item);
+    it = W == 1 ? next_item(a, n_items, dead) : next_item_wg(a, n_items, &s_item, dead);
   }
 }
 
@@ -2661,8 +2672,9 @@ __device__ __forceinline__ void p2pmix_loop(const RefineArgs &a, int persistent)
   int *slotseg = (int *)(tab + a.edge_chunk);
   int *slotf = slotseg + a.edge_chunk;
   const uint32_t n_items = *a.n_items;
-  uint32_t it = persistent ? (W == 1 ? next_item(a, n_items)
-                                      : next_item_wg(a, n_items, &s_item))
+  uint32_t dead = 0;  // queues this workgroup has found exhausted
+  uint32_t it = persistent ? (W == 1 ? next_item(a, n_items, dead)
+                                      : next_item_wg(a, n_items, &s_item, dead))
                            : blockIdx.x;
   while (it < n_items) {
     // A cell's last item holds the remainder of its points: with one wave per item it
@@ -2678,7 +2690,7 @@ __device__ __forceinline__ void p2pmix_loop(const RefineArgs &a, int persistent)
     else
       p2pmix_item<PPL, W, PRE>(a, item, U, V, tab, slotseg, slotf, red, smem);
     if (!persistent) break;
-    it = W == 1 ? next_item(a, n_items) : next_item_wg(a, n_items, &s_item);
+    it = W == 1 ? next_item(a, n_items, dead) : next_item_wg(a, n_items, &s_item, dead);
   }
 }
 
