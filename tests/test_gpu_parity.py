@@ -73,11 +73,33 @@ def pip_grid(gp, geom, params, prestage):
 # ---------------------------------------------------------------------------- pairing
 
 
-@pytest.mark.parametrize("case", ["c1", "c2", "c2_derived", "on_lines"])
+def exact_line_points(x0, y0, cs, nx, ny, rng):
+    """Points on the grid's cell lines (x0 + k cs rounded to a double, as the grid's own
+    division sees them), their neighbouring doubles on both sides, the far edges of the
+    extent, and non-finite and signed-zero coordinates."""
+    xs = x0 + np.arange(-1, nx + 2) * cs
+    ys = y0 + np.arange(-1, ny + 2) * cs
+    xs = np.concatenate([xs, np.nextafter(xs, -np.inf), np.nextafter(xs, np.inf)])
+    ys = np.concatenate([ys, np.nextafter(ys, -np.inf), np.nextafter(ys, np.inf)])
+    px = np.concatenate([rng.choice(xs, 40_000), rng.uniform(x0, x0 + nx * cs, 10_000),
+                         [np.nan, np.inf, -np.inf, 0.0, -0.0, x0, x0 + nx * cs]])
+    py = np.concatenate([rng.uniform(y0, y0 + ny * cs, 40_000), rng.choice(ys, 10_000),
+                         [0.5, 0.5, 0.5, -0.0, 0.0, y0 + ny * cs, y0]])
+    return px, py
+
+
+@pytest.mark.parametrize("case", ["c1", "c2", "c2_derived", "on_lines", "exact_lines"])
 def test_pairing_bit_exact(gp, case):
     say("pairing", case)
     if case == "c1":
         w = synth.config1()
+    elif case == "exact_lines":
+        # a cell size and origin that are not dyadic: x0 + k cs is rounded, and the
+        # cell of a point there is decided by the rounding of (x - x0) / cs
+        g = pins.polygons([[pins.box(0.35, 0.45, 1.15, 0.95)], [pins.box(-0.2, 0.1, 0.5, 0.7)]])
+        px, py = exact_line_points(-0.3, 0.1, 0.1, 17, 11, np.random.default_rng(5))
+        w = synth.Workload("exact_lines", "pip", g, px, py,
+                           synth.GridParams(cell_size=0.1, x0=-0.3, y0=0.1, nx=17, ny=11), {})
     elif case == "on_lines":
         g = pins.polygons([[pins.box(0.25, 0.5, 0.75, 0.625)], [pins.box(0.125, 0.0, 0.5, 0.25)]])
         rng = np.random.default_rng(3)
